@@ -1,0 +1,198 @@
+/*
+ * mhdc.h -- C-ABI of libmhdc.so: FP64 sparse matrix-vector multiplication
+ * y = A x in the M-HDC format on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Fukaya, Ishida, Miura, Iwashita, Nakashima, "Accelerating the SpMV
+ * kernel on standard CPUs by exploiting the partially diagonal structures",
+ * arXiv:2105.04937.
+ *
+ * Formats (all zero-based, FP64 values, INT32 indices, Sec. 3.1 and 6.1.2):
+ *   CSR    rowptr[n+1] (rowptr[0] = 0, rowptr[n] = nnz), colind[nnz],
+ *          val[nnz]; columns strictly increasing within a row (Sec. 3.2).
+ *   HDC    diagonals d = j - i with N(d)/n >= theta stored DIA-style over
+ *          all n rows, the other entries in a CSR part (Sec. 3.4).
+ *   M-HDC  rows cut into blocks of n_b rows; in block ib the partial
+ *          diagonals with N~(d,ib)/rows_ib >= theta are stored as n_b-long
+ *          value segments keyed by offset, the rest in a CSR remainder
+ *          (Sec. 4.3).  rows_ib = min(n_b, n - ib*n_b).
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer on the current HIP device
+ *     unless stated otherwise.  The caller keeps ownership of its arrays;
+ *     a handle owns copies of what it needs and frees them in *_destroy.
+ *   - *_from_csr is synchronous (it returns when the handle is complete).
+ *     *_spmv / *_spmm are asynchronous on the given stream (0 = the null
+ *     stream) and overwrite y (they do not accumulate).  x and y must not
+ *     overlap.  A handle is read-only after creation, so spmv calls on one
+ *     handle may run concurrently on several streams; *_destroy requires
+ *     that no work using the handle is still in flight.
+ *   - Functions returning int give MHDC_OK (0) or a negative MHDC_ERR_*
+ *     code; functions returning a handle give NULL on failure.  In both
+ *     cases the code and a message are kept per host thread
+ *     (mhdc_last_error, mhdc_last_error_message).
+ *   - Entries whose stored value compares equal to 0.0 (+0.0 or -0.0) never
+ *     count as nonzeros and always stay in the CSR part; DIA padding is
+ *     +0.0.  Results are promised for finite x (a padded 0 * Inf is NaN).
+ *   - The threshold test is (double)count / (double)rows >= theta in IEEE
+ *     FP64 with a correctly rounded division; a candidate diagonal needs at
+ *     least one nonzero (Sec. 3.3).  Offsets are d = j - i (the figures and
+ *     kernels of the paper index x[i + offset]).
+ */
+#ifndef MHDC_H
+#define MHDC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+enum {
+    MHDC_OK = 0,
+    MHDC_ERR_INVALID_ARG = -1,   /* bad size, NULL pointer, theta/n_b range */
+    MHDC_ERR_BAD_CSR = -2,       /* rowptr not monotone, rowptr[0] != 0,
+                                    column out of range, unsorted or
+                                    duplicate columns */
+    MHDC_ERR_OOM = -3,           /* device allocation failed or too large */
+    MHDC_ERR_HIP = -4,           /* a HIP runtime call failed */
+    MHDC_ERR_SIZE = -5,          /* a count does not fit the index types */
+    MHDC_ERR_NOT_SUPPORTED = -6  /* option outside the compiled variants */
+};
+
+/* Code of the last failure on the calling host thread (MHDC_OK if none). */
+int mhdc_last_error(void);
+/* Human-readable message of that failure (static storage, thread-local). */
+const char *mhdc_last_error_message(void);
+/* Name of an error code. */
+const char *mhdc_error_string(int code);
+
+/* ------------------------------------------------------------ handles */
+typedef struct mhdc_s *mhdc_handle;
+typedef struct hdc_s *hdc_handle;
+typedef struct csr_s *csr_handle;
+
+/* Sizes and model figures of a handle.  bytes_alg is what one spmv must
+ * move at the least with this layout (every stored array element read once,
+ * x read once, y written once):
+ *   8*S + 4*K + 4*(n_blk+1) + 12*R + (R > 0 ? 4*(n+1) : 0) + 16*n
+ * (CSR handles: 12*nnz + 4*(n+1) + 16*n).  bytes_paper is the paper's
+ * volume V = V_A + V_x + V_y with v_x = 1 (Eqs. 24/34 of Sec. 5.3):
+ *   12*R + 4*n + 8*S + 8*n + 8*n.  alpha and beta are the filling rate and
+ * CSR rate of Eqs. 23/33, rp_est the relative performance over CSR of
+ * Eq. 28 (1 + Eq. 28) with v_x = 1. */
+typedef struct {
+    int32_t kind;        /* 0 = M-HDC, 1 = HDC, 2 = CSR */
+    int32_t n;
+    int64_t nnz;         /* stored entries of the input CSR */
+    int32_t n_b;         /* rows per block (n for HDC, 0 for CSR) */
+    double theta;
+    int64_t n_blk;       /* number of row blocks */
+    int64_t K;           /* kept (partial) diagonals */
+    int64_t S;           /* DIA slots = K * n_b */
+    int64_t R;           /* entries in the CSR part / remainder */
+    double alpha, beta;
+    double bytes_alg, bytes_paper, rp_est;
+    int32_t rows_per_lane, wg_size, xcd_remap; /* current launch shape */
+} mhdc_info;
+
+/* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
+ * k = 1): rows each lane owns (spaced one wavefront apart); wg_size in
+ * {64, 256};
+ * xcd_remap != 0 maps workgroups so that each of the 8 XCDs walks one
+ * contiguous range of row tiles.  Set before use, not while spmv calls on
+ * the handle are in flight. */
+typedef struct {
+    int32_t rows_per_lane;
+    int32_t wg_size;
+    int32_t xcd_remap;
+} mhdc_launch;
+
+/* M-HDC conversion (Sec. 4.3, Figs. 14-15), all steps in HIP kernels:
+ * CSR validation, per-block census of nonzeros per offset, selection with
+ * the threshold rule, ascending order per block, scans of the per-block
+ * diagonal counts (dia_ptr) and per-row remainder counts, and the scatter
+ * into segment-local slots dia_val[k*n_b + (i - ib*n_b)].
+ * n >= 0; rowptr has n+1 entries; n_b >= 1; 0 <= threshold <= 1.
+ * Fails with BAD_CSR on malformed input, SIZE if nnz >= 2^31, OOM if the
+ * DIA part (8 * K * n_b bytes) does not fit. */
+mhdc_handle mhdc_from_csr(int32_t n, const int32_t *rowptr,
+                          const int32_t *colind, const double *val,
+                          int32_t n_b, double threshold);
+
+/* y = A x with the M-HDC kernel (Sec. 4.3, Fig. 16): per row block the
+ * CSR-remainder rows, then the block's partial diagonals, each y element
+ * written once.  x and y hold n doubles. */
+int mhdc_spmv(mhdc_handle h, const double *x, double *y, hipStream_t stream);
+
+/* Y = A X for k right-hand sides, 1 <= k <= 16, A read once per launch.
+ * Column r of X starts at X + r*ldx (ldx >= n), likewise Y with ldy. */
+int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
+              int64_t ldy, int32_t k, hipStream_t stream);
+
+/* Decode back to CSR on the device: rowptr[n+1], colind[nnz], val[nnz]
+ * (nnz from mhdc_get_info).  Row i merges, by column, its remainder entries
+ * and the nonzero slots of its block's partial diagonals; for canonical CSR
+ * input this is the identity, bit for bit.  Synchronous. */
+int mhdc_to_csr(mhdc_handle h, int32_t *rowptr, int32_t *colind, double *val);
+
+/* Copy the handle's arrays into caller buffers (device pointers, any may be
+ * NULL): dia_ptr[n_blk+1], dia_off[K], dia_val[S], rem_ptr[n+1],
+ * rem_col[R], rem_val[R].  Synchronous. */
+int mhdc_export(mhdc_handle h, int32_t *dia_ptr, int32_t *dia_off,
+                double *dia_val, int32_t *rem_ptr, int32_t *rem_col,
+                double *rem_val);
+
+int mhdc_get_info(mhdc_handle h, mhdc_info *out);
+int mhdc_set_launch(mhdc_handle h, const mhdc_launch *cfg);
+void mhdc_destroy(mhdc_handle h);
+
+/* HDC (Sec. 3.4, Figs. 6-8): global census N(d) over the whole matrix,
+ * d kept iff N(d)/n >= threshold, DIA values dia_val[k*n + i].  The spmv
+ * kernel is the cache-blocked B-HDC kernel (Sec. 4.2, Fig. 13): the format
+ * is M-HDC with a single block of n rows, which the paper notes selects the
+ * same diagonals (Sec. 6.4.2). */
+hdc_handle hdc_from_csr(int32_t n, const int32_t *rowptr,
+                        const int32_t *colind, const double *val,
+                        double threshold);
+int hdc_spmv(hdc_handle h, const double *x, double *y, hipStream_t stream);
+int hdc_spmm(hdc_handle h, const double *X, int64_t ldx, double *Y,
+             int64_t ldy, int32_t k, hipStream_t stream);
+int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val,
+               int32_t *rem_ptr, int32_t *rem_col, double *rem_val);
+int hdc_get_info(hdc_handle h, mhdc_info *out);
+int hdc_set_launch(hdc_handle h, const mhdc_launch *cfg);
+void hdc_destroy(hdc_handle h);
+
+/* Plain CSR baseline (Sec. 3.2, Fig. 3): the handle holds a validated copy
+ * of the CSR arrays; spmv stages each tile's entries through LDS with
+ * coalesced loads and sums every row in ascending column order. */
+csr_handle csr_from_csr(int32_t n, const int32_t *rowptr,
+                        const int32_t *colind, const double *val);
+int csr_spmv(csr_handle h, const double *x, double *y, hipStream_t stream);
+int csr_spmm(csr_handle h, const double *X, int64_t ldx, double *Y,
+             int64_t ldy, int32_t k, hipStream_t stream);
+int csr_get_info(csr_handle h, mhdc_info *out);
+int csr_set_launch(csr_handle h, const mhdc_launch *cfg);
+void csr_destroy(csr_handle h);
+
+/* -------------------------------------------------- memory benchmark */
+/* The two memory benchmark kernels of Sec. 6.2 (Figs. 19-20):
+ * direct C[i] += A[i]*B[i] (32 bytes per element) and indirect
+ * C[i] += A[i]*B[I[i]] (36 bytes per element).  Asynchronous. */
+int mhdc_stream_direct(int64_t N, const double *A, const double *B,
+                       double *C, hipStream_t stream);
+int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
+                         const int32_t *I, double *C, hipStream_t stream);
+
+/* ------------------------------------------------------ failure injection */
+/* Test hook: the countdown-th device allocation made by the library from now
+ * on fails with MHDC_ERR_OOM (0 disables).  Lets a host-side test drive every
+ * error path of a conversion and check that nothing leaks.  Process-wide. */
+int mhdc_debug_fail_alloc(int32_t countdown);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHDC_H */

@@ -1,0 +1,675 @@
+// converter.hip -- CSR -> M-HDC / HDC / CSR handles, and M-HDC -> CSR.
+//
+// Steps (M-HDC, Sec. 4.3; HDC, Sec. 3.4), each a HIP kernel:
+//   1. validate the CSR arrays (one lane per row, error bits in a flag);
+//   2. census: for each row block count the nonzeros of every offset
+//      d = j - i in an open-addressing hash table (LDS when the block holds
+//      fewer than CENSUS_LDS_SLOTS entries, else a per-block region of a
+//      global table); only integer atomics on counts, so the counted set
+//      does not depend on the order of the atomics;
+//   3. select offsets with count/rows >= theta and order each block's list
+//      ascending (rank sort: the kept offsets are distinct);
+//   4. scan the per-block counts into dia_ptr;
+//   5. scatter the kept nonzeros into dia_val[k*n_b + (i - ib*n_b)] and
+//      count, then scan and write, the CSR remainder row by row.
+// HDC counts N(d) over the whole matrix (per-chunk tables flushed into one
+// dense count array), keeps d with N(d)/n >= theta by an order-preserving
+// compaction, and is then laid out as one block of n rows.
+#include "internal.h"
+
+#include <climits>
+#include <vector>
+
+namespace mhdc {
+namespace {
+
+constexpr int CV_WG = 256;
+constexpr int CENSUS_LDS_SLOTS = 8192;      // LDS hash capacity (64 KB)
+constexpr int HDC_CENSUS_ROWS = 256;        // rows per HDC census chunk
+constexpr int32_t EMPTY_KEY = INT32_MIN;    // offsets lie in [-(n-1), n-1]
+
+inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 22)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- validate
+__global__ __launch_bounds__(CV_WG) void k_validate(int32_t n, int64_t nnz,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ colind,
+                                                    int32_t *flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        int64_t a = rowptr[i], b = rowptr[i + 1];
+        if (a > b || a < 0 || b > nnz) {
+            atomicOr(flag, 1);
+            continue;
+        }
+        int32_t prev = -1;
+        for (int64_t k = a; k < b; k++) {
+            int32_t c = colind[k];
+            if (c < 0 || c >= n || c <= prev) {
+                atomicOr(flag, 2);
+                break;
+            }
+            prev = c;
+        }
+    }
+}
+
+// Largest number of stored entries in one block of n_b rows.
+__global__ __launch_bounds__(CV_WG) void k_block_max(int32_t n, int32_t n_b, int64_t n_blk,
+                                                     const int32_t *__restrict__ rowptr,
+                                                     int32_t *out)
+{
+    int32_t best = 0;
+    for (int64_t ib = (int64_t)blockIdx.x * CV_WG + threadIdx.x; ib < n_blk;
+         ib += (int64_t)gridDim.x * CV_WG) {
+        int64_t r0 = ib * n_b, r1 = min((int64_t)n, r0 + n_b);
+        best = max(best, rowptr[r1] - rowptr[r0]);
+    }
+    atomicMax(out, best);
+}
+
+// ---------------------------------------------------------------- census
+__device__ inline uint32_t key_hash(int32_t d, uint32_t cap)
+{
+    return ((uint32_t)d * 2654435761u) % cap;
+}
+
+// Count one occurrence of key d.  The table has more slots than distinct
+// keys can occur (cap > entries of the block), so probing terminates.
+__device__ inline void table_add(int32_t *keys, int32_t *cnts, uint32_t cap, int32_t d)
+{
+    uint32_t h = key_hash(d, cap);
+    for (;;) {
+        int32_t prev = atomicCAS(&keys[h], EMPTY_KEY, d);
+        if (prev == EMPTY_KEY || prev == d) {
+            atomicAdd(&cnts[h], 1);
+            return;
+        }
+        h = (h + 1 == cap) ? 0 : h + 1;
+    }
+}
+
+// mode 0 (M-HDC): per block, select and sort the kept offsets:
+//   Kb[ib] = number kept, sel_tmp[e0 .. e0+Kb) = kept offsets ascending,
+//   with e0 = rowptr[ib*n_b] (a block keeps at most its entry count).
+// mode 1 (HDC census): add each block's counts into hdc_count[d + n - 1].
+__global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n_b, int64_t n_blk,
+                                                  const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind,
+                                                  const double *__restrict__ val, double theta,
+                                                  int32_t *Kb, int32_t *sel_tmp, int32_t *list_tmp,
+                                                  int32_t *gkeys, int32_t *gcnts,
+                                                  int32_t *hdc_count)
+{
+    __shared__ int32_t s_keys[CENSUS_LDS_SLOTS];
+    __shared__ int32_t s_cnts[CENSUS_LDS_SLOTS];
+    __shared__ int32_t s_nsel;
+
+    for (int64_t ib = blockIdx.x; ib < n_blk; ib += gridDim.x) {
+        const int64_t r0 = ib * n_b, r1 = min((int64_t)n, r0 + n_b);
+        const int64_t rows = r1 - r0;
+        const int64_t e0 = rowptr[r0], e1 = rowptr[r1];
+        const int64_t m = e1 - e0;
+
+        int32_t *keys, *cnts;
+        uint32_t cap;
+        if (m < CENSUS_LDS_SLOTS) {
+            keys = s_keys;
+            cnts = s_cnts;
+            uint32_t c = 64;
+            while (c < 2 * (uint32_t)m && c < CENSUS_LDS_SLOTS)
+                c <<= 1;
+            cap = c > (uint32_t)m ? c : (uint32_t)CENSUS_LDS_SLOTS;
+        } else {
+            keys = gkeys + 2 * e0;
+            cnts = gcnts + 2 * e0;
+            cap = (uint32_t)(2 * m);
+        }
+        for (uint32_t s = threadIdx.x; s < cap; s += CV_WG) {
+            keys[s] = EMPTY_KEY;
+            cnts[s] = 0;
+        }
+        if (threadIdx.x == 0)
+            s_nsel = 0;
+        __syncthreads();
+
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += CV_WG) {
+            const int32_t a = rowptr[i], b = rowptr[i + 1];
+            for (int32_t k = a; k < b; k++)
+                if (val[k] != 0.0)
+                    table_add(keys, cnts, cap, colind[k] - (int32_t)i);
+        }
+        __syncthreads();
+
+        for (uint32_t s = threadIdx.x; s < cap; s += CV_WG) {
+            const int32_t key = keys[s];
+            if (key == EMPTY_KEY)
+                continue;
+            const int32_t c = cnts[s];
+            if (mode == 1) {
+                atomicAdd(&hdc_count[(int64_t)key + n - 1], c);
+            } else if (c >= 1 && (double)c / (double)rows >= theta) {
+                int32_t p = atomicAdd(&s_nsel, 1);
+                list_tmp[e0 + p] = key;
+            }
+        }
+        __syncthreads();
+
+        if (mode == 0) {
+            const int32_t nsel = s_nsel;
+            for (int32_t s = threadIdx.x; s < nsel; s += CV_WG) {
+                const int32_t key = list_tmp[e0 + s];
+                int32_t rank = 0;
+                for (int32_t t = 0; t < nsel; t++)
+                    rank += list_tmp[e0 + t] < key;
+                sel_tmp[e0 + rank] = key;
+            }
+            if (threadIdx.x == 0)
+                Kb[ib] = nsel;
+        }
+        __syncthreads();
+    }
+}
+
+// dia_off[dia_ptr[ib] + t] = sel_tmp[rowptr[ib*n_b] + t]
+__global__ __launch_bounds__(CV_WG) void k_gather_offsets(int32_t n_b, int64_t n_blk,
+                                                          const int32_t *__restrict__ rowptr,
+                                                          const int32_t *__restrict__ dia_ptr,
+                                                          const int32_t *__restrict__ sel_tmp,
+                                                          int32_t *dia_off)
+{
+    for (int64_t ib = blockIdx.x; ib < n_blk; ib += gridDim.x) {
+        const int64_t e0 = rowptr[ib * n_b];
+        const int32_t k0 = dia_ptr[ib], kb = dia_ptr[ib + 1] - k0;
+        for (int32_t t = threadIdx.x; t < kb; t += CV_WG)
+            dia_off[k0 + t] = sel_tmp[e0 + t];
+    }
+}
+
+// HDC: flag[q] = 1 iff offset q - (n-1) is kept (N(d)/n >= theta).
+__global__ __launch_bounds__(CV_WG) void k_hdc_flags(int32_t n, int64_t span,
+                                                     const int32_t *__restrict__ cnt,
+                                                     double theta, int32_t *flag)
+{
+    for (int64_t q = (int64_t)blockIdx.x * CV_WG + threadIdx.x; q < span;
+         q += (int64_t)gridDim.x * CV_WG) {
+        const int32_t c = cnt[q];
+        flag[q] = (c >= 1 && (double)c / (double)n >= theta) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(CV_WG) void k_hdc_compact(int32_t n, int64_t span,
+                                                       const int32_t *__restrict__ flag,
+                                                       const int32_t *__restrict__ pos,
+                                                       int32_t *dia_off)
+{
+    for (int64_t q = (int64_t)blockIdx.x * CV_WG + threadIdx.x; q < span;
+         q += (int64_t)gridDim.x * CV_WG)
+        if (flag[q])
+            dia_off[pos[q]] = (int32_t)(q - (n - 1));
+}
+
+__global__ __launch_bounds__(CV_WG) void k_fill_f64(double *p, int64_t count, double v)
+{
+    for (int64_t s = (int64_t)blockIdx.x * CV_WG + threadIdx.x; s < count;
+         s += (int64_t)gridDim.x * CV_WG)
+        p[s] = v;
+}
+
+// Position of offset d in the block's ascending list dia_off[lo, hi), or -1.
+__device__ inline int32_t find_offset(const int32_t *__restrict__ dia_off, int32_t lo,
+                                      int32_t hi, int32_t d)
+{
+    int32_t a = lo, b = hi;
+    while (a < b) {
+        int32_t mid = (a + b) >> 1;
+        if (dia_off[mid] < d)
+            a = mid + 1;
+        else
+            b = mid;
+    }
+    return (a < hi && dia_off[a] == d) ? a : -1;
+}
+
+// Scatter the kept nonzeros of every row into its segment slot and count
+// the entries left for the remainder.
+__global__ __launch_bounds__(CV_WG) void k_split_rows(int32_t n, int32_t n_b,
+                                                      const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ colind,
+                                                      const double *__restrict__ val,
+                                                      const int32_t *__restrict__ dia_ptr,
+                                                      const int32_t *__restrict__ dia_off,
+                                                      double *dia_val, int32_t *remcnt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int64_t ib = i / n_b, t = i - ib * n_b;
+        const int32_t kb0 = dia_ptr[ib], kb1 = dia_ptr[ib + 1];
+        int32_t cnt = 0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; k++) {
+            const double v = val[k];
+            int32_t p = -1;
+            if (v != 0.0 && kb1 > kb0)
+                p = find_offset(dia_off, kb0, kb1, colind[k] - (int32_t)i);
+            if (p >= 0)
+                dia_val[(int64_t)p * n_b + t] = v;
+            else
+                cnt++;
+        }
+        remcnt[i] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(CV_WG) void k_scatter_rem(int32_t n, int32_t n_b,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ colind,
+                                                       const double *__restrict__ val,
+                                                       const int32_t *__restrict__ dia_ptr,
+                                                       const int32_t *__restrict__ dia_off,
+                                                       const int32_t *__restrict__ rem_ptr,
+                                                       int32_t *rem_col, double *rem_val)
+{
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int64_t ib = i / n_b;
+        const int32_t kb0 = dia_ptr[ib], kb1 = dia_ptr[ib + 1];
+        int32_t q = rem_ptr[i];
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; k++) {
+            const double v = val[k];
+            const int32_t c = colind[k];
+            int32_t p = -1;
+            if (v != 0.0 && kb1 > kb0)
+                p = find_offset(dia_off, kb0, kb1, c - (int32_t)i);
+            if (p < 0) {
+                rem_col[q] = c;
+                rem_val[q] = v;
+                q++;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- decode
+__global__ __launch_bounds__(CV_WG) void k_decode_count(int32_t n, int32_t n_b,
+                                                        const int32_t *__restrict__ dia_ptr,
+                                                        const int32_t *__restrict__ dia_off,
+                                                        const double *__restrict__ dia_val,
+                                                        const int32_t *__restrict__ rem_ptr,
+                                                        int32_t *cnt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int64_t ib = i / n_b, t = i - ib * n_b;
+        int32_t c = rem_ptr[i + 1] - rem_ptr[i];
+        for (int32_t k = dia_ptr[ib]; k < dia_ptr[ib + 1]; k++) {
+            const int64_t j = i + dia_off[k];
+            if (j >= 0 && j < n && dia_val[(int64_t)k * n_b + t] != 0.0)
+                c++;
+        }
+        cnt[i] = c;
+    }
+}
+
+__global__ __launch_bounds__(CV_WG) void k_decode_write(int32_t n, int32_t n_b,
+                                                        const int32_t *__restrict__ dia_ptr,
+                                                        const int32_t *__restrict__ dia_off,
+                                                        const double *__restrict__ dia_val,
+                                                        const int32_t *__restrict__ rem_ptr,
+                                                        const int32_t *__restrict__ rem_col,
+                                                        const double *__restrict__ rem_val,
+                                                        const int32_t *__restrict__ out_ptr,
+                                                        int32_t *out_col, double *out_val)
+{
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int64_t ib = i / n_b, t = i - ib * n_b;
+        int32_t k = dia_ptr[ib];
+        const int32_t kend = dia_ptr[ib + 1];
+        int32_t q = rem_ptr[i];
+        const int32_t qend = rem_ptr[i + 1];
+        int32_t e = out_ptr[i];
+        for (;;) {
+            while (k < kend) {
+                const int64_t j = i + dia_off[k];
+                if (j >= 0 && j < n && dia_val[(int64_t)k * n_b + t] != 0.0)
+                    break;
+                k++;
+            }
+            const bool hd = k < kend, hr = q < qend;
+            if (!hd && !hr)
+                break;
+            const bool take_d = hd && (!hr || (int64_t)i + dia_off[k] < rem_col[q]);
+            if (take_d) {
+                out_col[e] = (int32_t)(i + dia_off[k]);
+                out_val[e] = dia_val[(int64_t)k * n_b + t];
+                k++;
+            } else {
+                out_col[e] = rem_col[q];
+                out_val[e] = rem_val[q];
+                q++;
+            }
+            e++;
+        }
+    }
+}
+
+// Frees every pointer registered with it unless release() was called.
+struct TempSet {
+    std::vector<void *> ptrs;
+    void *add(void *p)
+    {
+        ptrs.push_back(p);
+        return p;
+    }
+    ~TempSet()
+    {
+        for (void *p : ptrs)
+            dfree(p);
+    }
+};
+
+int launch_ok(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MHDC_OK;
+}
+
+int sync_ok(const char *what)
+{
+    hipError_t e = hipStreamSynchronize(0);
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return launch_ok(what);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+int validate_csr(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                 int64_t *nnz_out)
+{
+    if (n < 0)
+        return set_error(MHDC_ERR_INVALID_ARG, "n must be >= 0");
+    if (!rowptr)
+        return set_error(MHDC_ERR_INVALID_ARG, "rowptr is NULL");
+    int32_t ends[2] = {0, 0};
+    MHDC_HIP_CHECK(hipMemcpy(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+    MHDC_HIP_CHECK(hipMemcpy(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (ends[0] != 0)
+        return set_error(MHDC_ERR_BAD_CSR, "rowptr[0] must be 0");
+    if (ends[1] < 0)
+        return set_error(MHDC_ERR_BAD_CSR, "rowptr[n] (nnz) is negative");
+    const int64_t nnz = ends[1];
+    if (nnz >= (int64_t)INT32_MAX)
+        return set_error(MHDC_ERR_SIZE, "nnz must be < 2^31 - 1");
+    if (nnz > 0 && (!colind || !val))
+        return set_error(MHDC_ERR_INVALID_ARG, "colind/val is NULL");
+    if (n > 0) {
+        int32_t *flag = nullptr;
+        int rc = dmalloc((void **)&flag, sizeof(int32_t), "validation flag");
+        if (rc)
+            return rc;
+        (void)hipMemsetAsync(flag, 0, sizeof(int32_t), 0);
+        k_validate<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, nnz, rowptr, colind, flag);
+        int32_t h = 0;
+        hipError_t e = hipMemcpy(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost);
+        dfree(flag);
+        if (e != hipSuccess)
+            return set_error(MHDC_ERR_HIP, std::string("validation: ") + hipGetErrorString(e));
+        if (h & 1)
+            return set_error(MHDC_ERR_BAD_CSR, "rowptr is not non-decreasing within [0, nnz]");
+        if (h & 2)
+            return set_error(MHDC_ERR_BAD_CSR,
+                             "column index out of range, unsorted or duplicated in a row");
+    }
+    *nnz_out = nnz;
+    return MHDC_OK;
+}
+
+void free_matrix(BdcMatrix &m)
+{
+    dfree(m.dia_ptr);
+    dfree(m.dia_off);
+    dfree(m.dia_val);
+    dfree(m.rem_ptr);
+    dfree(m.rem_col);
+    dfree(m.rem_val);
+    m.dia_ptr = m.dia_off = m.rem_ptr = m.rem_col = nullptr;
+    m.dia_val = m.rem_val = nullptr;
+}
+
+int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const double *val)
+{
+    const int32_t n = m.n;
+    int64_t nnz = 0;
+    int rc = validate_csr(n, rowptr, colind, val, &nnz);
+    if (rc)
+        return rc;
+    m.nnz = nnz;
+    if (m.kind == KIND_HDC)
+        m.n_b = n > 0 ? n : 1;
+    const int32_t n_b = m.n_b;
+    const int64_t n_blk = n == 0 ? 0 : ((int64_t)n + n_b - 1) / n_b;
+    m.n_blk = n_blk;
+
+    TempSet tmp;
+    rc = dmalloc((void **)&m.dia_ptr, sizeof(int32_t) * (size_t)(n_blk + 1), "dia_ptr");
+    if (rc)
+        return rc;
+    rc = dmalloc((void **)&m.rem_ptr, sizeof(int32_t) * (size_t)(n + 1), "rem_ptr");
+    if (rc)
+        return rc;
+    if (n == 0) {
+        MHDC_HIP_CHECK(hipMemset(m.dia_ptr, 0, sizeof(int32_t)));
+        MHDC_HIP_CHECK(hipMemset(m.rem_ptr, 0, sizeof(int32_t)));
+        return MHDC_OK;
+    }
+    const size_t nz1 = (size_t)(nnz > 0 ? nnz : 1);
+
+    int64_t K = 0;
+    if (m.kind == KIND_MHDC) {
+        int32_t *Kb = nullptr, *sel_tmp = nullptr, *list_tmp = nullptr, *bmax = nullptr;
+        int32_t *gkeys = nullptr, *gcnts = nullptr;
+        if ((rc = dmalloc((void **)&Kb, sizeof(int32_t) * (size_t)n_blk, "block counts")))
+            return rc;
+        tmp.add(Kb);
+        if ((rc = dmalloc((void **)&sel_tmp, sizeof(int32_t) * nz1, "census list")))
+            return rc;
+        tmp.add(sel_tmp);
+        if ((rc = dmalloc((void **)&list_tmp, sizeof(int32_t) * nz1, "census list")))
+            return rc;
+        tmp.add(list_tmp);
+        if ((rc = dmalloc((void **)&bmax, sizeof(int32_t), "block max")))
+            return rc;
+        tmp.add(bmax);
+        MHDC_HIP_CHECK(hipMemsetAsync(bmax, 0, sizeof(int32_t), 0));
+        k_block_max<<<grid_for(n_blk, CV_WG, 1 << 14), CV_WG, 0, 0>>>(n, n_b, n_blk, rowptr, bmax);
+        int32_t hmax = 0;
+        MHDC_HIP_CHECK(hipMemcpy(&hmax, bmax, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (hmax >= CENSUS_LDS_SLOTS) {
+            if ((rc = dmalloc((void **)&gkeys, sizeof(int32_t) * 2 * nz1, "census table")))
+                return rc;
+            tmp.add(gkeys);
+            if ((rc = dmalloc((void **)&gcnts, sizeof(int32_t) * 2 * nz1, "census table")))
+                return rc;
+            tmp.add(gcnts);
+        }
+        k_census<<<grid_for(n_blk, 1, 1 << 20), CV_WG, 0, 0>>>(
+            0, n, n_b, n_blk, rowptr, colind, val, m.theta, Kb, sel_tmp, list_tmp, gkeys, gcnts,
+            nullptr);
+        if ((rc = launch_ok("census")))
+            return rc;
+        if ((rc = exclusive_scan_i32(Kb, m.dia_ptr, n_blk, &K, 0)))
+            return rc;
+        m.K = K;
+        if (K > 0) {
+            if ((rc = dmalloc((void **)&m.dia_off, sizeof(int32_t) * (size_t)K, "dia_off")))
+                return rc;
+            k_gather_offsets<<<grid_for(n_blk, 1, 1 << 20), CV_WG, 0, 0>>>(
+                n_b, n_blk, rowptr, m.dia_ptr, sel_tmp, m.dia_off);
+            if ((rc = launch_ok("gather offsets")))
+                return rc;
+        }
+    } else {
+        // HDC: global census over chunks, then select over all offsets.
+        const int64_t span = 2 * (int64_t)n - 1;
+        const int64_t n_chunk = ((int64_t)n + HDC_CENSUS_ROWS - 1) / HDC_CENSUS_ROWS;
+        int32_t *gcount = nullptr, *flag = nullptr, *pos = nullptr, *gkeys = nullptr,
+                *gcnts = nullptr, *bmax = nullptr;
+        if ((rc = dmalloc((void **)&gcount, sizeof(int32_t) * (size_t)span, "offset counts")))
+            return rc;
+        tmp.add(gcount);
+        MHDC_HIP_CHECK(hipMemsetAsync(gcount, 0, sizeof(int32_t) * (size_t)span, 0));
+        if ((rc = dmalloc((void **)&bmax, sizeof(int32_t), "block max")))
+            return rc;
+        tmp.add(bmax);
+        MHDC_HIP_CHECK(hipMemsetAsync(bmax, 0, sizeof(int32_t), 0));
+        k_block_max<<<grid_for(n_chunk, CV_WG, 1 << 14), CV_WG, 0, 0>>>(n, HDC_CENSUS_ROWS,
+                                                                        n_chunk, rowptr, bmax);
+        int32_t hmax = 0;
+        MHDC_HIP_CHECK(hipMemcpy(&hmax, bmax, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (hmax >= CENSUS_LDS_SLOTS) {
+            if ((rc = dmalloc((void **)&gkeys, sizeof(int32_t) * 2 * nz1, "census table")))
+                return rc;
+            tmp.add(gkeys);
+            if ((rc = dmalloc((void **)&gcnts, sizeof(int32_t) * 2 * nz1, "census table")))
+                return rc;
+            tmp.add(gcnts);
+        }
+        k_census<<<grid_for(n_chunk, 1, 1 << 20), CV_WG, 0, 0>>>(
+            1, n, HDC_CENSUS_ROWS, n_chunk, rowptr, colind, val, m.theta, nullptr, nullptr,
+            nullptr, gkeys, gcnts, gcount);
+        if ((rc = launch_ok("hdc census")))
+            return rc;
+        if ((rc = dmalloc((void **)&flag, sizeof(int32_t) * (size_t)span, "offset flags")))
+            return rc;
+        tmp.add(flag);
+        if ((rc = dmalloc((void **)&pos, sizeof(int32_t) * (size_t)(span + 1), "offset pos")))
+            return rc;
+        tmp.add(pos);
+        k_hdc_flags<<<grid_for(span, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, span, gcount, m.theta,
+                                                                     flag);
+        if ((rc = exclusive_scan_i32(flag, pos, span, &K, 0)))
+            return rc;
+        m.K = K;
+        int32_t hptr[2] = {0, (int32_t)K};
+        MHDC_HIP_CHECK(hipMemcpy(m.dia_ptr, hptr, sizeof(hptr), hipMemcpyHostToDevice));
+        if (K > 0) {
+            if ((rc = dmalloc((void **)&m.dia_off, sizeof(int32_t) * (size_t)K, "dia_off")))
+                return rc;
+            k_hdc_compact<<<grid_for(span, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, span, flag, pos,
+                                                                           m.dia_off);
+            if ((rc = launch_ok("hdc compact")))
+                return rc;
+        }
+    }
+
+    // DIA values: K * n_b slots, +0.0 padding.
+    m.S = K * (int64_t)n_b;
+    if (m.S > 0) {
+        size_t fr = 0, tot = 0;
+        MHDC_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+        const double need = 8.0 * (double)m.S;
+        if (need > (double)fr)
+            return set_error(MHDC_ERR_OOM, "DIA part needs " + std::to_string(need / 1e9) +
+                                               " GB, " + std::to_string(fr / 1e9) + " GB free");
+        if ((rc = dmalloc((void **)&m.dia_val, sizeof(double) * (size_t)m.S, "dia_val")))
+            return rc;
+        k_fill_f64<<<grid_for(m.S, CV_WG, 1 << 16), CV_WG, 0, 0>>>(m.dia_val, m.S, 0.0);
+    }
+
+    int32_t *remcnt = nullptr;
+    if ((rc = dmalloc((void **)&remcnt, sizeof(int32_t) * (size_t)n, "remainder counts")))
+        return rc;
+    tmp.add(remcnt);
+    k_split_rows<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, n_b, rowptr, colind, val,
+                                                               m.dia_ptr, m.dia_off, m.dia_val,
+                                                               remcnt);
+    if ((rc = launch_ok("split rows")))
+        return rc;
+    int64_t R = 0;
+    if ((rc = exclusive_scan_i32(remcnt, m.rem_ptr, n, &R, 0)))
+        return rc;
+    m.R = R;
+    if (R > 0) {
+        if ((rc = dmalloc((void **)&m.rem_col, sizeof(int32_t) * (size_t)R, "rem_col")))
+            return rc;
+        if ((rc = dmalloc((void **)&m.rem_val, sizeof(double) * (size_t)R, "rem_val")))
+            return rc;
+        k_scatter_rem<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(
+            n, n_b, rowptr, colind, val, m.dia_ptr, m.dia_off, m.rem_ptr, m.rem_col, m.rem_val);
+    }
+    return sync_ok("conversion");
+}
+
+int build_csr(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const double *val)
+{
+    const int32_t n = m.n;
+    int64_t nnz = 0;
+    int rc = validate_csr(n, rowptr, colind, val, &nnz);
+    if (rc)
+        return rc;
+    m.nnz = nnz;
+    m.n_b = 0;
+    m.n_blk = 0;
+    m.K = m.S = 0;
+    m.R = nnz;
+    if ((rc = dmalloc((void **)&m.rem_ptr, sizeof(int32_t) * (size_t)(n + 1), "rowptr")))
+        return rc;
+    MHDC_HIP_CHECK(hipMemcpy(m.rem_ptr, rowptr, sizeof(int32_t) * (size_t)(n + 1),
+                             hipMemcpyDeviceToDevice));
+    if (nnz > 0) {
+        if ((rc = dmalloc((void **)&m.rem_col, sizeof(int32_t) * (size_t)nnz, "colind")))
+            return rc;
+        if ((rc = dmalloc((void **)&m.rem_val, sizeof(double) * (size_t)nnz, "val")))
+            return rc;
+        MHDC_HIP_CHECK(hipMemcpy(m.rem_col, colind, sizeof(int32_t) * (size_t)nnz,
+                                 hipMemcpyDeviceToDevice));
+        MHDC_HIP_CHECK(hipMemcpy(m.rem_val, val, sizeof(double) * (size_t)nnz,
+                                 hipMemcpyDeviceToDevice));
+    }
+    return sync_ok("csr copy");
+}
+
+int decode_to_csr(const BdcMatrix &m, int32_t *rowptr, int32_t *colind, double *val)
+{
+    const int32_t n = m.n;
+    if (!rowptr)
+        return set_error(MHDC_ERR_INVALID_ARG, "rowptr is NULL");
+    if (n == 0) {
+        MHDC_HIP_CHECK(hipMemset(rowptr, 0, sizeof(int32_t)));
+        return MHDC_OK;
+    }
+    if (m.nnz > 0 && (!colind || !val))
+        return set_error(MHDC_ERR_INVALID_ARG, "colind/val is NULL");
+    TempSet tmp;
+    int32_t *cnt = nullptr;
+    int rc = dmalloc((void **)&cnt, sizeof(int32_t) * (size_t)n, "decode counts");
+    if (rc)
+        return rc;
+    tmp.add(cnt);
+    k_decode_count<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, m.n_b, m.dia_ptr, m.dia_off,
+                                                                 m.dia_val, m.rem_ptr, cnt);
+    int64_t total = 0;
+    if ((rc = exclusive_scan_i32(cnt, rowptr, n, &total, 0)))
+        return rc;
+    if (total != m.nnz)
+        return set_error(MHDC_ERR_BAD_CSR, "decoded entry count differs from nnz");
+    k_decode_write<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(
+        n, m.n_b, m.dia_ptr, m.dia_off, m.dia_val, m.rem_ptr, m.rem_col, m.rem_val, rowptr,
+        colind, val);
+    return sync_ok("decode");
+}
+
+}  // namespace mhdc

@@ -1,0 +1,74 @@
+// internal.h -- shared declarations of libmhdc (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mhdc.h"
+
+namespace mhdc {
+
+enum Kind : int32_t { KIND_MHDC = 0, KIND_HDC = 1, KIND_CSR = 2 };
+
+// Row-blocked DIA part plus CSR remainder.  M-HDC uses n_b rows per block;
+// HDC is the one-block case (n_b = n); CSR has no DIA part (K = 0) and its
+// remainder is the whole matrix.
+struct BdcMatrix {
+    int32_t kind = KIND_MHDC;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t n_b = 1;
+    double theta = 0.0;
+    int64_t n_blk = 0;
+    int64_t K = 0, S = 0, R = 0;
+    int32_t *dia_ptr = nullptr;  // [n_blk+1]
+    int32_t *dia_off = nullptr;  // [K]
+    double *dia_val = nullptr;   // [S]
+    int32_t *rem_ptr = nullptr;  // [n+1]
+    int32_t *rem_col = nullptr;  // [R]
+    double *rem_val = nullptr;   // [R]
+    int device = 0;
+    mhdc_launch launch{2, 256, 1};
+};
+
+// Thread-local error state.
+int set_error(int code, const std::string &msg);
+void clear_error();
+
+// Device memory helpers that record errors.
+int dmalloc(void **p, size_t bytes, const char *what);
+void dfree(void *p);
+
+#define MHDC_HIP_CHECK(call)                                                  \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return ::mhdc::set_error(MHDC_ERR_HIP,                            \
+                                     std::string(#call " failed: ") +         \
+                                         hipGetErrorString(e_));              \
+    } while (0)
+
+// converter.hip
+int validate_csr(int32_t n, const int32_t *rowptr, const int32_t *colind,
+                 const double *val, int64_t *nnz_out);
+int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind,
+                  const double *val);  // M-HDC (m.kind = MHDC) or HDC
+int build_csr(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind,
+              const double *val);
+int decode_to_csr(const BdcMatrix &m, int32_t *rowptr, int32_t *colind,
+                  double *val);
+void free_matrix(BdcMatrix &m);
+
+// spmv.hip
+int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y,
+                int64_t ldy, int32_t k, hipStream_t stream);
+int check_launch(const mhdc_launch &cfg);
+
+// scan.hip: exclusive prefix sum of cnt[0..N) into out[0..N] (out[N] =
+// total), all int32 on the device; total also returned on the host.
+int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
+                       int64_t *total, hipStream_t stream);
+
+}  // namespace mhdc

@@ -1,0 +1,303 @@
+"""Thin ctypes binding of libmhdc.so (the C-ABI of include/mhdc.h).
+
+Argument marshalling only: every step of conversion and SpMV runs in the HIP
+kernels of the library.  torch tensors provide device memory and streams.
+If the library has not been built, loading raises RuntimeError; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhdc.so")
+
+KIND_MHDC, KIND_HDC, KIND_CSR = 0, 1, 2
+ERRORS = {0: "MHDC_OK", -1: "MHDC_ERR_INVALID_ARG", -2: "MHDC_ERR_BAD_CSR", -3: "MHDC_ERR_OOM",
+          -4: "MHDC_ERR_HIP", -5: "MHDC_ERR_SIZE", -6: "MHDC_ERR_NOT_SUPPORTED"}
+
+
+class MhdcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("n_b", ctypes.c_int32), ("theta", ctypes.c_double), ("n_blk", ctypes.c_int64),
+                ("K", ctypes.c_int64), ("S", ctypes.c_int64), ("R", ctypes.c_int64),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("bytes_alg", ctypes.c_double), ("bytes_paper", ctypes.c_double),
+                ("rp_est", ctypes.c_double), ("rows_per_lane", ctypes.c_int32),
+                ("wg_size", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+
+# name -> (restype, argtypes); every exported symbol of include/mhdc.h
+SIGNATURES = {
+    "mhdc_last_error": (ctypes.c_int, []),
+    "mhdc_last_error_message": (ctypes.c_char_p, []),
+    "mhdc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mhdc_from_csr": (_vp, [_i32, _vp, _vp, _vp, _i32, _f64]),
+    "mhdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mhdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "mhdc_to_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "mhdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mhdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "mhdc_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
+    "mhdc_destroy": (None, [_vp]),
+    "hdc_from_csr": (_vp, [_i32, _vp, _vp, _vp, _f64]),
+    "hdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "hdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "hdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "hdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "hdc_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
+    "hdc_destroy": (None, [_vp]),
+    "csr_from_csr": (_vp, [_i32, _vp, _vp, _vp]),
+    "csr_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "csr_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "csr_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "csr_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
+    "csr_destroy": (None, [_vp]),
+    "mhdc_stream_direct": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp]),
+    "mhdc_stream_indirect": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp, _vp]),
+    "mhdc_debug_fail_alloc": (ctypes.c_int, [_i32]),
+}
+
+
+def lib():
+    """Load libmhdc.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmhdc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _raise(code=None):
+    L = lib()
+    c = L.mhdc_last_error() if code is None else code
+    raise MhdcError(c, (L.mhdc_last_error_message() or b"").decode())
+
+
+def _check(rc):
+    if rc != 0:
+        _raise(rc)
+
+
+def _dptr(t, dtype, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _Matrix:
+    _prefix = ""
+    kind = -1
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    def _fn(self, suffix):
+        return getattr(lib(), self._prefix + suffix)
+
+    def info(self) -> dict:
+        out = Info()
+        _check(self._fn("get_info")(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def set_launch(self, rows_per_lane=2, wg_size=256, xcd_remap=1):
+        cfg = Launch(rows_per_lane, wg_size, xcd_remap)
+        _check(self._fn("set_launch")(self._h, ctypes.byref(cfg)))
+        return self
+
+    def spmv(self, x, y=None, stream=None):
+        """y = A x (overwrites y); x, y float64 device vectors of length n."""
+        if x.numel() != self.n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), self.n))
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        _check(self._fn("spmv")(self._h, _dptr(x, torch.float64, "x"),
+                                _dptr(y, torch.float64, "y"), _stream(stream)))
+        return y
+
+    def spmm(self, X, Y=None, stream=None):
+        """Y = A X for k right-hand sides given as rows of X, shape (k, n)
+        contiguous (column-major (n, k) in the C-ABI, ldx = n)."""
+        if X.dim() != 2 or X.shape[1] != self.n:
+            raise ValueError("X must have shape (k, n)")
+        k = X.shape[0]
+        if Y is None:
+            Y = torch.empty((k, self.n), dtype=torch.float64, device=X.device)
+        _check(self._fn("spmm")(self._h, _dptr(X, torch.float64, "X"), self.n,
+                                _dptr(Y, torch.float64, "Y"), self.n, k, _stream(stream)))
+        return Y
+
+    def close(self):
+        if self._h:
+            self._fn("destroy")(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _csr_args(rowptr, colind, val):
+    # conversion runs on the null stream; make torch's producers finish first
+    torch.cuda.current_stream().synchronize()
+    n = rowptr.numel() - 1
+    return (n, _dptr(rowptr, torch.int32, "rowptr"), _dptr(colind, torch.int32, "colind"),
+            _dptr(val, torch.float64, "val"))
+
+
+class MHDCMatrix(_Matrix):
+    """M-HDC handle (Sec. 4.3 of the paper): per-block partial diagonals with
+    N~(d,ib)/rows_ib >= theta as n_b-long segments, the rest as CSR."""
+    _prefix = "mhdc_"
+    kind = KIND_MHDC
+
+    @classmethod
+    def from_csr(cls, rowptr, colind, val, n_b: int, theta: float):
+        n, rp, ci, v = _csr_args(rowptr, colind, val)
+        h = lib().mhdc_from_csr(n, rp, ci, v, int(n_b), float(theta))
+        if not h:
+            _raise()
+        return cls(h, n)
+
+    def export(self):
+        """Device copies of dia_ptr, dia_off, dia_val, rem_ptr, rem_col, rem_val."""
+        inf = self.info()
+        dev = torch.device("cuda")
+        t = dict(dia_ptr=torch.empty(inf["n_blk"] + 1, dtype=torch.int32, device=dev),
+                 dia_off=torch.empty(inf["K"], dtype=torch.int32, device=dev),
+                 dia_val=torch.empty(inf["S"], dtype=torch.float64, device=dev),
+                 rem_ptr=torch.empty(inf["n"] + 1, dtype=torch.int32, device=dev),
+                 rem_col=torch.empty(inf["R"], dtype=torch.int32, device=dev),
+                 rem_val=torch.empty(inf["R"], dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        _check(lib().mhdc_export(self._h, *[_dptr(t[k], t[k].dtype, k) for k in
+                                            ("dia_ptr", "dia_off", "dia_val", "rem_ptr",
+                                             "rem_col", "rem_val")]))
+        return t
+
+    def to_csr(self):
+        """Decode on the device back to (rowptr, colind, val)."""
+        inf = self.info()
+        dev = torch.device("cuda")
+        rp = torch.empty(inf["n"] + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(inf["nnz"], dtype=torch.int32, device=dev)
+        v = torch.empty(inf["nnz"], dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        _check(lib().mhdc_to_csr(self._h, _dptr(rp, torch.int32, "rowptr"),
+                                 _dptr(ci, torch.int32, "colind"), _dptr(v, torch.float64, "val")))
+        return rp, ci, v
+
+
+class HDCMatrix(_Matrix):
+    """HDC handle (Sec. 3.4): global diagonals with N(d)/n >= theta plus CSR;
+    its kernel is the cache-blocked B-HDC kernel (Sec. 4.2)."""
+    _prefix = "hdc_"
+    kind = KIND_HDC
+
+    @classmethod
+    def from_csr(cls, rowptr, colind, val, theta: float):
+        n, rp, ci, v = _csr_args(rowptr, colind, val)
+        h = lib().hdc_from_csr(n, rp, ci, v, float(theta))
+        if not h:
+            _raise()
+        return cls(h, n)
+
+    def export(self):
+        inf = self.info()
+        dev = torch.device("cuda")
+        t = dict(dia_off=torch.empty(inf["K"], dtype=torch.int32, device=dev),
+                 dia_val=torch.empty(inf["S"], dtype=torch.float64, device=dev),
+                 rem_ptr=torch.empty(inf["n"] + 1, dtype=torch.int32, device=dev),
+                 rem_col=torch.empty(inf["R"], dtype=torch.int32, device=dev),
+                 rem_val=torch.empty(inf["R"], dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        _check(lib().hdc_export(self._h, *[_dptr(t[k], t[k].dtype, k) for k in
+                                           ("dia_off", "dia_val", "rem_ptr", "rem_col",
+                                            "rem_val")]))
+        return t
+
+
+class CSRMatrix(_Matrix):
+    """Plain CSR baseline handle (Sec. 3.2)."""
+    _prefix = "csr_"
+    kind = KIND_CSR
+
+    @classmethod
+    def from_csr(cls, rowptr, colind, val):
+        n, rp, ci, v = _csr_args(rowptr, colind, val)
+        h = lib().csr_from_csr(n, rp, ci, v)
+        if not h:
+            _raise()
+        return cls(h, n)
+
+
+def stream_direct(A, B, C, stream=None):
+    """C += A * B elementwise (memory benchmark, Sec. 6.2)."""
+    _check(lib().mhdc_stream_direct(C.numel(), _dptr(A, torch.float64, "A"),
+                                    _dptr(B, torch.float64, "B"), _dptr(C, torch.float64, "C"),
+                                    _stream(stream)))
+    return C
+
+
+def stream_indirect(A, B, I, C, stream=None):
+    """C += A * B[I] elementwise (memory benchmark, Sec. 6.2)."""
+    _check(lib().mhdc_stream_indirect(C.numel(), _dptr(A, torch.float64, "A"),
+                                      _dptr(B, torch.float64, "B"), _dptr(I, torch.int32, "I"),
+                                      _dptr(C, torch.float64, "C"), _stream(stream)))
+    return C
+
+
+def to_device(m, device="cuda"):
+    """Copy a synth.CSRMatrix to device tensors (rowptr, colind, val)."""
+    return (torch.from_numpy(m.rowptr).to(device), torch.from_numpy(m.colind).to(device),
+            torch.from_numpy(m.val).to(device))

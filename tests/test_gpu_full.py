@@ -1,0 +1,116 @@
+"""GPU parity at the full workload sizes, in the launch shape the benchmark
+times: the 7-point Laplacian on 32^3 (n_b = 256), the heptadiagonal 256^3
+matrix over n_b = 128..4096, and the partially diagonal 27-point 192^3
+matrix.  Conversions are compared with the oracle bit for bit, every SpMV
+element-wise against the oracle within 1e-13 * (|A||x|)_i."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_04937_amd import mhdc, synth
+from tests.gpu_helpers import (assert_spmv_close, check_hdc_arrays, check_mhdc_arrays,
+                               check_round_trip, dev, say)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+class Case:
+    def __init__(self, m, xseed):
+        self.m = m
+        self.x = synth.vector(m.n, xseed)
+        self.yref = oracle.csr_spmv(m.rowptr, m.colind, m.val, self.x, 0)
+        self.scale = oracle.csr_absmv(m.rowptr, m.colind, m.val, self.x)
+        self.d = dev(m)
+        self.xd = torch.from_numpy(self.x).cuda()
+
+    def check(self, mat, shapes=((2, 256, 1),)):
+        for shp in shapes:
+            mat.set_launch(*shp)
+            assert_spmv_close(mat.spmv(self.xd), self.m, self.x, Y_ref=self.yref,
+                              absAx=self.scale)
+
+
+@pytest.fixture(scope="module")
+def lap32():
+    say("generating 7-point Laplacian 32^3")
+    return Case(synth.laplacian7(32), 1)
+
+
+@pytest.fixture(scope="module")
+def hepta256():
+    say("generating heptadiagonal 256^3")
+    return Case(synth.heptadiagonal(256, 2), 2)
+
+
+@pytest.fixture(scope="module")
+def partial192():
+    say("generating partially diagonal 27-point 192^3")
+    return Case(synth.partially_diagonal(192, 3), 3)
+
+
+def test_laplacian32(lap32):
+    c, m = lap32, lap32.m
+    say("case: laplacian 32^3 n_b=256")
+    h = mhdc.MHDCMatrix.from_csr(*c.d, 256, 0.6)
+    check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6))
+    check_round_trip(h, m)
+    c.check(h, shapes=((1, 64, 1), (2, 256, 1), (4, 256, 0)))
+    # linear field: the product is exact and equals the oracle's bits
+    N = 32
+    r = np.arange(m.n)
+    xl = 3.0 * (r % N) - 2.0 * ((r // N) % N) + 5.0 * (r // (N * N)) + 7.0
+    want = oracle.csr_spmv(m.rowptr, m.colind, m.val, xl)
+    assert np.array_equal(h.spmv(torch.from_numpy(xl).cuda()).cpu().numpy(), want)
+    hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
+    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
+    c.check(hd)
+    c.check(mhdc.CSRMatrix.from_csr(*c.d))
+
+
+@pytest.mark.parametrize("n_b", [128, 256, 512, 1024, 2048, 4096])
+def test_hepta256_spmv(hepta256, n_b):
+    c = hepta256
+    say("case: heptadiagonal 256^3 n_b=%d" % n_b)
+    h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, 0.6)
+    inf = h.info()
+    assert inf["nnz"] == 117_047_296
+    if n_b == 256:
+        assert (inf["K"], inf["S"], inf["R"]) == (457_728, 117_178_368, 0)
+        assert abs(inf["bytes_alg"] - 1_207_955_460) < 1
+    c.check(h, shapes=((2, 256, 1), (1, 64, 1)))
+    if n_b in (256, 4096):
+        check_mhdc_arrays(h, oracle.mhdc_from_csr(c.m.rowptr, c.m.colind, c.m.val, n_b, 0.6))
+        check_round_trip(h, c.m)
+
+
+def test_hepta256_hdc_csr(hepta256):
+    c, m = hepta256, hepta256.m
+    say("case: heptadiagonal 256^3 HDC + CSR")
+    hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
+    assert hd.info()["K"] == 7
+    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
+    c.check(hd)
+    c.check(mhdc.CSRMatrix.from_csr(*c.d))
+
+
+@pytest.mark.parametrize("n_b", [32, 96, 128, 256])
+def test_partial192_mhdc(partial192, n_b):
+    c, m = partial192, partial192.m
+    say("case: partially diagonal 192^3 n_b=%d" % n_b)
+    h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, 0.6)
+    c.check(h, shapes=((2, 256, 1), (1, 64, 1)))
+    if n_b == 128:
+        check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, 0.6))
+        check_round_trip(h, m)
+        inf = h.info()
+        assert 0.8 < inf["alpha"] < 0.95 and 0.2 < inf["beta"] < 0.3
+
+
+def test_partial192_hdc_csr(partial192):
+    c, m = partial192, partial192.m
+    say("case: partially diagonal 192^3 HDC + CSR")
+    hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
+    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
+    c.check(hd)
+    c.check(mhdc.CSRMatrix.from_csr(*c.d))

@@ -1,0 +1,277 @@
+"""GPU parity on small inputs: the paper's worked example, brute-force random
+matrices with ragged blocks, degenerate shapes, every launch shape, several
+right-hand sides, error paths.  Every call goes through the C-ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_04937_amd import mhdc, synth
+from tests.conftest import load_golden
+from tests.gpu_helpers import (assert_same_bits, assert_spmv_close, check_hdc_arrays,
+                               check_mhdc_arrays, check_round_trip, dev, say)
+
+pytestmark = pytest.mark.gpu
+
+THETAS = [0.0, 0.5, 0.6, 2.0 / 3.0, 0.75, 1.0]
+SHAPES = [(1, 64, 0), (1, 64, 1), (2, 64, 1), (4, 64, 1), (1, 256, 1), (2, 256, 0),
+          (2, 256, 1), (4, 256, 1)]
+
+
+def _example_csr():
+    rows = np.array(load_golden("example_matrix.txt")["row"], dtype=np.float64)
+    m = synth.CSRMatrix(8, *(lambda r, c: (
+        np.concatenate([[0], np.cumsum(np.bincount(r, minlength=8))]).astype(np.int32),
+        c.astype(np.int32), rows[r, c]))(*np.nonzero(rows)), meta=dict(seed=0))
+    return m
+
+
+def test_example_matrix_mhdc_hdc_csr():
+    say("case: Example matrix, bl=4 theta=0.6")
+    m = _example_csr()
+    rp, ci, v = dev(m)
+    g = load_golden("example_products.txt")
+    h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, 0.6)
+    check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 4, 0.6))
+    f15 = load_golden("example_mhdc_bl4_theta0.6.txt")
+    t = h.export()
+    assert t["dia_off"].cpu().tolist() == [int(a) for a in f15["dia_col_offset"][0]]
+    hd = mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6)
+    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
+    cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
+    for x, y in zip(g["x"], g["y"]):
+        xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+        for mat in (h, hd, cs):
+            got = mat.spmv(xd).cpu().numpy()
+            assert np.array_equal(got, np.array(y)), (mat, got)
+    check_round_trip(h, m)
+
+
+def _cases():
+    out = []
+    for s, n in enumerate([1, 2, 5, 8, 17, 33, 64, 100, 257]):
+        bands = [0, 1, -1, 3, -(n // 2)] if n > 2 else [0]
+        out.append(synth.random_csr(n, 100 + s, density=min(0.08, 8.0 / n), bands=bands,
+                                    int_values=True))
+        out.append(synth.random_csr(n, 200 + s, density=min(0.3, 16.0 / n)))
+    out.append(synth.random_csr(40, 300, density=0.05, bands=[0, 2, -5], zero_frac=0.2,
+                                int_values=True))
+    out.append(synth.random_csr(10, 301, density=0.0))  # no stored entries
+    out.append(synth.random_csr(700, 302, density=0.004, bands=[0, 1, -1, 30, -30, 300],
+                                band_fill=0.8))
+    return out
+
+
+@pytest.mark.parametrize("m", _cases(), ids=lambda m: "n%d_s%d" % (m.n, m.meta["seed"]))
+def test_random_conversion_and_spmv(m):
+    say("case: random n=%d seed=%d nnz=%d" % (m.n, m.meta["seed"], m.nnz))
+    rp, ci, v = dev(m)
+    x = synth.vector(m.n, 3)
+    xd = torch.from_numpy(x).cuda()
+    yref = oracle.csr_spmv(m.rowptr, m.colind, m.val, x)
+    for bl in (1, 3, 4, 32, 64, 128, 1000):
+        for theta in THETAS:
+            ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, theta)
+            h = mhdc.MHDCMatrix.from_csr(rp, ci, v, bl, theta)
+            check_mhdc_arrays(h, ref)
+            check_round_trip(h, m)
+            assert_spmv_close(h.spmv(xd), m, x, Y_ref=yref)
+            h.close()
+    for theta in THETAS:
+        ref = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, theta)
+        hd = mhdc.HDCMatrix.from_csr(rp, ci, v, theta)
+        check_hdc_arrays(hd, ref)
+        assert_spmv_close(hd.spmv(xd), m, x, Y_ref=yref)
+    cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
+    y = assert_spmv_close(cs.spmv(xd), m, x, Y_ref=yref)
+    if np.all(m.val == np.round(m.val)):
+        xi = np.arange(m.n, dtype=np.float64) - 5.0
+        want = oracle.csr_spmv(m.rowptr, m.colind, m.val, xi)
+        xid = torch.from_numpy(xi).cuda()
+        for mat in (mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, 0.5), cs,
+                    mhdc.HDCMatrix.from_csr(rp, ci, v, 0.5)):
+            assert np.array_equal(mat.spmv(xid).cpu().numpy(), want)
+    del y
+
+
+def test_launch_shapes_give_identical_bits():
+    """Each row sums its remainder entries in column order and then its
+    diagonals in offset order whatever the launch shape, so every shape
+    returns the same bits."""
+    m = synth.partially_diagonal(20, 11, drop=synth.OCTANT_DROP)
+    say("case: launch shapes, n=%d nnz=%d" % (m.n, m.nnz))
+    rp, ci, v = dev(m)
+    x = synth.vector(m.n, 4)
+    xd = torch.from_numpy(x).cuda()
+    for bl, theta in ((20, 0.6), (64, 0.6), (128, 0.5), (256, 0.9), (48, 0.6)):
+        h = mhdc.MHDCMatrix.from_csr(rp, ci, v, bl, theta)
+        first = None
+        for shp in SHAPES:
+            h.set_launch(*shp)
+            y = h.spmv(xd).cpu().numpy()
+            if first is None:
+                first = y
+                assert_spmv_close(y, m, x)
+            assert_same_bits(y, first, "shape %s bl %d" % (shp, bl))
+            assert_same_bits(h.spmv(xd).cpu().numpy(), first, "repeat")
+    cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
+    first = None
+    for shp in SHAPES:
+        cs.set_launch(*shp)
+        y = cs.spmv(xd).cpu().numpy()
+        first = y if first is None else first
+        assert_same_bits(y, first, "csr shape %s" % (shp,))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 11, 16])
+def test_multi_rhs(k):
+    m = synth.partially_diagonal(14, 21, drop=0.2)
+    say("case: spmm k=%d n=%d" % (k, m.n))
+    rp, ci, v = dev(m)
+    X = np.ascontiguousarray(np.random.default_rng(k).uniform(-1, 1, size=(k, m.n)))
+    Xd = torch.from_numpy(X).cuda()
+    Yref = oracle.csr_spmm(m.rowptr, m.colind, m.val, np.asfortranarray(X.T))
+    mats = [mhdc.MHDCMatrix.from_csr(rp, ci, v, 64, 0.6), mhdc.MHDCMatrix.from_csr(rp, ci, v, 14, 0.6),
+            mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6), mhdc.CSRMatrix.from_csr(rp, ci, v)]
+    for mat in mats:
+        for shp in ((1, 64, 1), (2, 256, 1), (4, 256, 0)):
+            mat.set_launch(*shp)
+            Y = mat.spmm(Xd).cpu().numpy()
+            for r in range(k):
+                assert_spmv_close(Y[r], m, X[r], Y_ref=Yref[:, r])
+                # one right-hand side alone gives the same bits
+                y1 = mat.spmv(Xd[r].contiguous()).cpu().numpy()
+                assert_same_bits(Y[r], y1, "rhs %d" % r)
+
+
+def test_degenerate_shapes():
+    say("case: degenerate shapes")
+    # n = 0
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ci = torch.zeros(0, dtype=torch.int32, device="cuda")
+    v = torch.zeros(0, dtype=torch.float64, device="cuda")
+    for mat in (mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, 0.6), mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6),
+                mhdc.CSRMatrix.from_csr(rp, ci, v)):
+        y = mat.spmv(torch.zeros(0, dtype=torch.float64, device="cuda"))
+        assert y.numel() == 0
+    # n = 1 with one entry; a matrix of empty rows; n_b = 1 and n_b >= n
+    for m in (synth.random_csr(1, 5, density=1.0), synth.random_csr(50, 6, density=0.0),
+              synth.random_csr(3, 7, density=1.0)):
+        rp, ci, v = dev(m)
+        x = synth.vector(m.n, 1)
+        xd = torch.from_numpy(x).cuda()
+        for bl in (1, 2, m.n, 10 * m.n + 3):
+            h = mhdc.MHDCMatrix.from_csr(rp, ci, v, bl, 0.6)
+            check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, 0.6))
+            assert_spmv_close(h.spmv(xd), m, x)
+
+
+def test_signed_zero_nan_round_trip():
+    m = synth.random_csr(90, 8, density=0.02, bands=[0, 1, -2, 7], band_fill=1.0)
+    v = m.val.copy()
+    v[::7] = -0.0
+    v[3] = np.inf
+    v[5] = -np.inf
+    v[11] = np.nan
+    m = synth.CSRMatrix(m.n, m.rowptr, m.colind, v, m.meta)
+    say("case: signed zero / NaN round trip")
+    rp, ci, vd = dev(m)
+    for bl in (4, 32, 90):
+        h = mhdc.MHDCMatrix.from_csr(rp, ci, vd, bl, 0.5)
+        check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, 0.5))
+        check_round_trip(h, m)
+
+
+def test_error_paths():
+    say("case: error paths")
+    m = synth.random_csr(20, 9, density=0.2, bands=[0])
+    rp, ci, v = dev(m)
+    with pytest.raises(mhdc.MhdcError) as e:
+        mhdc.MHDCMatrix.from_csr(rp, ci, v, 0, 0.6)
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    for th in (float("nan"), -0.1, 1.5):
+        with pytest.raises(mhdc.MhdcError) as e:
+            mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, th)
+        assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    # unsorted / duplicate / out-of-range columns, broken rowptr
+    bad = []
+    c2 = m.colind.copy()
+    r = int(np.argmax(np.diff(m.rowptr) >= 2))
+    a = m.rowptr[r]
+    c2[a], c2[a + 1] = c2[a + 1], c2[a]
+    bad.append((m.rowptr, c2))
+    c3 = m.colind.copy()
+    c3[a + 1] = c3[a]
+    bad.append((m.rowptr, c3))
+    c4 = m.colind.copy()
+    c4[0] = m.n
+    bad.append((m.rowptr, c4))
+    p5 = m.rowptr.copy()
+    p5[3] = p5[4] + 1
+    bad.append((p5, m.colind))
+    p6 = m.rowptr.copy()
+    p6[0] = 1
+    bad.append((p6, m.colind))
+    for p, c in bad:
+        pd, cd = torch.from_numpy(p).cuda(), torch.from_numpy(c).cuda()
+        for make in (lambda: mhdc.MHDCMatrix.from_csr(pd, cd, v, 4, 0.6),
+                     lambda: mhdc.HDCMatrix.from_csr(pd, cd, v, 0.6),
+                     lambda: mhdc.CSRMatrix.from_csr(pd, cd, v)):
+            with pytest.raises(mhdc.MhdcError) as e:
+                make()
+            assert e.value.name == "MHDC_ERR_BAD_CSR"
+    h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, 0.6)
+    buf = torch.zeros(2 * m.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(mhdc.MhdcError) as e:
+        h.spmv(buf[:m.n], buf[m.n // 2: m.n // 2 + m.n])  # overlapping x and y
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    X = torch.zeros((17, m.n), dtype=torch.float64, device="cuda")
+    with pytest.raises(mhdc.MhdcError):
+        h.spmm(X)
+    with pytest.raises(mhdc.MhdcError) as e:
+        h.set_launch(3, 256, 1)
+    assert e.value.name == "MHDC_ERR_NOT_SUPPORTED"
+
+
+def test_allocation_failure_leaks_nothing():
+    """Fail the k-th device allocation of a conversion for every k: each
+    attempt reports MHDC_ERR_OOM and returns all memory it took."""
+    m = synth.partially_diagonal(12, 13)
+    say("case: injected allocation failures")
+    rp, ci, v = dev(m)
+    L = mhdc.lib()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for make in (lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, 32, 0.6),
+                 lambda: mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6),
+                 lambda: mhdc.CSRMatrix.from_csr(rp, ci, v)):
+        k = 1
+        while True:
+            L.mhdc_debug_fail_alloc(k)
+            try:
+                h = make()
+            except mhdc.MhdcError as e:
+                assert e.name == "MHDC_ERR_OOM"
+                k += 1
+                continue
+            finally:
+                L.mhdc_debug_fail_alloc(0)
+            h.close()
+            break
+        assert k > 2
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (4 << 20)
+
+
+def test_memory_benchmark_kernels():
+    say("case: memory benchmark kernels")
+    N = 100_003
+    rng = np.random.default_rng(0)
+    A, B, C = rng.random(N), rng.random(N), rng.random(N)
+    I = np.arange(N, dtype=np.int32)
+    Ad, Bd, Cd, Id = (torch.from_numpy(t).cuda() for t in (A, B, C, I))
+    mhdc.stream_direct(Ad, Bd, Cd)
+    assert np.allclose(Cd.cpu().numpy(), oracle.stream_direct(A, B, C), rtol=1e-15, atol=0)
+    Cd2 = torch.from_numpy(C).cuda()
+    mhdc.stream_indirect(Ad, Bd, Id, Cd2)
+    assert np.allclose(Cd2.cpu().numpy(), oracle.stream_indirect(A, B, I, C), rtol=1e-15, atol=0)
