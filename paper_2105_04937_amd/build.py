@@ -22,7 +22,7 @@ ARCH = "gfx950"
 CFLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-ffp-contract=fast",
+    "-ffp-contract=off",
 ]
 
 

@@ -62,6 +62,10 @@ int decode_to_csr(const BdcMatrix &m, int32_t *rowptr, int32_t *colind,
 void free_matrix(BdcMatrix &m);
 
 // spmv.hip
+struct SpmvArgs;
+int kc_for(int k);
+int check_operands(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
+                   int64_t ldy, int32_t k);
 int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y,
                 int64_t ldy, int32_t k, hipStream_t stream);
 int check_launch(const mhdc_launch &cfg);

@@ -73,3 +73,9 @@ def check_round_trip(h, m):
     assert_same_bits(rp.cpu().numpy(), m.rowptr, "rowptr")
     assert_same_bits(ci.cpu().numpy(), m.colind, "colind")
     assert_same_bits(v.cpu().numpy(), m.val, "val")
+
+
+def assert_oracle_bits(y_gpu, y_oracle, name):
+    """The GPU kernel reproduces the paper's sequential kernel bit for bit."""
+    y = y_gpu.detach().cpu().numpy() if isinstance(y_gpu, torch.Tensor) else y_gpu
+    assert_same_bits(y, y_oracle, name)

@@ -9,8 +9,8 @@ import torch
 
 import oracle
 from paper_2105_04937_amd import mhdc, synth
-from tests.gpu_helpers import (assert_spmv_close, check_hdc_arrays, check_mhdc_arrays,
-                               check_round_trip, dev, say)
+from tests.gpu_helpers import (assert_oracle_bits, assert_spmv_close, check_hdc_arrays,
+                               check_mhdc_arrays, check_round_trip, dev, say)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -24,11 +24,17 @@ class Case:
         self.d = dev(m)
         self.xd = torch.from_numpy(self.x).cuda()
 
-    def check(self, mat, shapes=((2, 256, 1),)):
+    def check(self, mat, shapes=((2, 256, 1),), want=None):
+        """Within 1e-13 |A||x| of the CSR definition; bit-identical to the
+        oracle's sequential kernel `want` (CSR: the oracle's CSR product)."""
+        if want is None and isinstance(mat, mhdc.CSRMatrix):
+            want = self.yref
         for shp in shapes:
             mat.set_launch(*shp)
-            assert_spmv_close(mat.spmv(self.xd), self.m, self.x, Y_ref=self.yref,
-                              absAx=self.scale)
+            y = mat.spmv(self.xd)
+            assert_spmv_close(y, self.m, self.x, Y_ref=self.yref, absAx=self.scale)
+            if want is not None:
+                assert_oracle_bits(y, want, "launch %s" % (shp,))
 
 
 @pytest.fixture(scope="module")
@@ -53,9 +59,10 @@ def test_laplacian32(lap32):
     c, m = lap32, lap32.m
     say("case: laplacian 32^3 n_b=256")
     h = mhdc.MHDCMatrix.from_csr(*c.d, 256, 0.6)
-    check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6))
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6)
+    check_mhdc_arrays(h, ref)
     check_round_trip(h, m)
-    c.check(h, shapes=((1, 64, 1), (2, 256, 1), (4, 256, 0)))
+    c.check(h, shapes=((1, 64, 1), (2, 256, 1), (4, 256, 0)), want=oracle.mhdc_spmv(ref, c.x))
     # linear field: the product is exact and equals the oracle's bits
     N = 32
     r = np.arange(m.n)
@@ -63,8 +70,9 @@ def test_laplacian32(lap32):
     want = oracle.csr_spmv(m.rowptr, m.colind, m.val, xl)
     assert np.array_equal(h.spmv(torch.from_numpy(xl).cuda()).cpu().numpy(), want)
     hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
-    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
-    c.check(hd)
+    rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
+    check_hdc_arrays(hd, rh)
+    c.check(hd, want=oracle.hdc_spmv(rh, c.x))
     c.check(mhdc.CSRMatrix.from_csr(*c.d))
 
 
@@ -78,10 +86,13 @@ def test_hepta256_spmv(hepta256, n_b):
     if n_b == 256:
         assert (inf["K"], inf["S"], inf["R"]) == (457_728, 117_178_368, 0)
         assert abs(inf["bytes_alg"] - 1_207_955_460) < 1
-    c.check(h, shapes=((2, 256, 1), (1, 64, 1)))
+    want = None
     if n_b in (256, 4096):
-        check_mhdc_arrays(h, oracle.mhdc_from_csr(c.m.rowptr, c.m.colind, c.m.val, n_b, 0.6))
+        ref = oracle.mhdc_from_csr(c.m.rowptr, c.m.colind, c.m.val, n_b, 0.6)
+        check_mhdc_arrays(h, ref)
         check_round_trip(h, c.m)
+        want = oracle.mhdc_spmv(ref, c.x)
+    c.check(h, shapes=((2, 256, 1), (1, 64, 1), (4, 256, 1)), want=want)
 
 
 def test_hepta256_hdc_csr(hepta256):
@@ -89,8 +100,9 @@ def test_hepta256_hdc_csr(hepta256):
     say("case: heptadiagonal 256^3 HDC + CSR")
     hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
     assert hd.info()["K"] == 7
-    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
-    c.check(hd)
+    rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
+    check_hdc_arrays(hd, rh)
+    c.check(hd, want=oracle.hdc_spmv(rh, c.x))
     c.check(mhdc.CSRMatrix.from_csr(*c.d))
 
 
@@ -99,10 +111,14 @@ def test_partial192_mhdc(partial192, n_b):
     c, m = partial192, partial192.m
     say("case: partially diagonal 192^3 n_b=%d" % n_b)
     h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, 0.6)
-    c.check(h, shapes=((2, 256, 1), (1, 64, 1)))
+    want = None
     if n_b == 128:
-        check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, 0.6))
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, 0.6)
+        check_mhdc_arrays(h, ref)
         check_round_trip(h, m)
+        want = oracle.mhdc_spmv(ref, c.x)
+    c.check(h, shapes=((2, 256, 1), (1, 64, 1)), want=want)
+    if n_b == 128:
         inf = h.info()
         assert 0.8 < inf["alpha"] < 0.95 and 0.2 < inf["beta"] < 0.3
 
@@ -111,6 +127,7 @@ def test_partial192_hdc_csr(partial192):
     c, m = partial192, partial192.m
     say("case: partially diagonal 192^3 HDC + CSR")
     hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
-    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6))
-    c.check(hd)
-    c.check(mhdc.CSRMatrix.from_csr(*c.d))
+    rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
+    check_hdc_arrays(hd, rh)
+    c.check(hd, want=oracle.hdc_spmv(rh, c.x))
+    c.check(mhdc.CSRMatrix.from_csr(*c.d), shapes=((2, 256, 1), (1, 64, 1)))

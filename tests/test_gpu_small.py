@@ -8,8 +8,8 @@ import torch
 import oracle
 from paper_2105_04937_amd import mhdc, synth
 from tests.conftest import load_golden
-from tests.gpu_helpers import (assert_same_bits, assert_spmv_close, check_hdc_arrays,
-                               check_mhdc_arrays, check_round_trip, dev, say)
+from tests.gpu_helpers import (assert_oracle_bits, assert_same_bits, assert_spmv_close,
+                               check_hdc_arrays, check_mhdc_arrays, check_round_trip, dev, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -75,15 +75,20 @@ def test_random_conversion_and_spmv(m):
             h = mhdc.MHDCMatrix.from_csr(rp, ci, v, bl, theta)
             check_mhdc_arrays(h, ref)
             check_round_trip(h, m)
-            assert_spmv_close(h.spmv(xd), m, x, Y_ref=yref)
+            y = h.spmv(xd)
+            assert_spmv_close(y, m, x, Y_ref=yref)
+            assert_oracle_bits(y, oracle.mhdc_spmv(ref, x), "mhdc bl=%d theta=%g" % (bl, theta))
             h.close()
     for theta in THETAS:
         ref = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, theta)
         hd = mhdc.HDCMatrix.from_csr(rp, ci, v, theta)
         check_hdc_arrays(hd, ref)
-        assert_spmv_close(hd.spmv(xd), m, x, Y_ref=yref)
+        y = hd.spmv(xd)
+        assert_spmv_close(y, m, x, Y_ref=yref)
+        assert_oracle_bits(y, oracle.hdc_spmv(ref, x), "hdc theta=%g" % theta)
     cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
-    y = assert_spmv_close(cs.spmv(xd), m, x, Y_ref=yref)
+    y = cs.spmv(xd)
+    assert_oracle_bits(y, yref, "csr")
     if np.all(m.val == np.round(m.val)):
         xi = np.arange(m.n, dtype=np.float64) - 5.0
         want = oracle.csr_spmv(m.rowptr, m.colind, m.val, xi)
@@ -105,6 +110,7 @@ def test_launch_shapes_give_identical_bits():
     xd = torch.from_numpy(x).cuda()
     for bl, theta in ((20, 0.6), (64, 0.6), (128, 0.5), (256, 0.9), (48, 0.6)):
         h = mhdc.MHDCMatrix.from_csr(rp, ci, v, bl, theta)
+        want = oracle.mhdc_spmv(oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, theta), x)
         first = None
         for shp in SHAPES:
             h.set_launch(*shp)
@@ -113,6 +119,7 @@ def test_launch_shapes_give_identical_bits():
                 first = y
                 assert_spmv_close(y, m, x)
             assert_same_bits(y, first, "shape %s bl %d" % (shp, bl))
+            assert_oracle_bits(y, want, "shape %s bl %d" % (shp, bl))
             assert_same_bits(h.spmv(xd).cpu().numpy(), first, "repeat")
     cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
     first = None
@@ -133,7 +140,10 @@ def test_multi_rhs(k):
     Yref = oracle.csr_spmm(m.rowptr, m.colind, m.val, np.asfortranarray(X.T))
     mats = [mhdc.MHDCMatrix.from_csr(rp, ci, v, 64, 0.6), mhdc.MHDCMatrix.from_csr(rp, ci, v, 14, 0.6),
             mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6), mhdc.CSRMatrix.from_csr(rp, ci, v)]
-    for mat in mats:
+    refs = [oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 64, 0.6),
+            oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 14, 0.6),
+            oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6), None]
+    for mat, ref in zip(mats, refs):
         for shp in ((1, 64, 1), (2, 256, 1), (4, 256, 0)):
             mat.set_launch(*shp)
             Y = mat.spmm(Xd).cpu().numpy()
@@ -142,6 +152,13 @@ def test_multi_rhs(k):
                 # one right-hand side alone gives the same bits
                 y1 = mat.spmv(Xd[r].contiguous()).cpu().numpy()
                 assert_same_bits(Y[r], y1, "rhs %d" % r)
+                if ref is None:
+                    want = Yref[:, r]
+                elif ref.n_blk == 1 and ref.bl == m.n and isinstance(mat, mhdc.HDCMatrix):
+                    want = oracle.hdc_spmv(ref, X[r])
+                else:
+                    want = oracle.mhdc_spmv(ref, X[r])
+                assert_oracle_bits(Y[r], want, "rhs %d" % r)
 
 
 def test_degenerate_shapes():
