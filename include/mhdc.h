@@ -186,6 +186,71 @@ int mhdc_stream_direct(int64_t N, const double *A, const double *B,
 int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
                          const int32_t *I, double *C, hipStream_t stream);
 
+/* ---------------------------------------------- batched persistent launch */
+/* Many M-HDC products in one launch.  Not in the paper; it addresses the
+ * under-filled machine the paper reports when a matrix has too few row
+ * blocks for the threads (Secs. 6.4.2-6.4.3, matrix #17).  All tiles of
+ * all items form one sequence; a persistent grid of (CUs x resident
+ * workgroups) takes tiles from an atomic counter until none is left.  Each
+ * tile writes only its own rows, so item i's result is bit-identical to
+ * mhdc_spmm(mats[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i]).
+ *
+ * mats[count]: M-HDC handles (not owned; must outlive the batch).
+ * nrhs[count]: right-hand sides per item, 1..16.
+ * X[count], Y[count]: HOST arrays of DEVICE pointers, column-major blocks
+ * with leading dimensions ldx[i], ldy[i] >= n_i (NULL ldx/ldy = n_i).
+ * wg_size: 64 or 256 lanes per workgroup (mhdc_batch_tune picks).
+ * Y blocks must not overlap any X block. */
+typedef struct mhdc_batch_s *mhdc_batch;
+typedef struct {
+    int32_t count, wg_size;
+    int64_t total_tiles;
+    int32_t grid;          /* persistent workgroups per launch */
+    double flops;          /* sum of 2 * nnz_i * nrhs_i */
+    double bytes_alg;      /* sum of algorithmic bytes (A once, X once, Y once) */
+} mhdc_batch_info;
+
+mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats,
+                             const int32_t *nrhs, const double *const *X,
+                             const int64_t *ldx, double *const *Y,
+                             const int64_t *ldy, int32_t wg_size);
+/* Replace the X/Y pointers (synchronous; waits for work in flight).  A
+ * captured graph reads the table from device memory and sees the change. */
+int mhdc_batch_bind(mhdc_batch b, const double *const *X, const int64_t *ldx,
+                    double *const *Y, const int64_t *ldy);
+/* Enqueue counter reset + persistent kernel on `stream` (asynchronous). */
+int mhdc_batch_run(mhdc_batch b, hipStream_t stream);
+/* First call captures the reset + persistent kernel into a HIP graph (on an
+ * internal stream, no memset node); every call launches that graph on
+ * `stream`.  Asynchronous. */
+int mhdc_batch_graph_launch(mhdc_batch b, hipStream_t stream);
+int mhdc_batch_set_wg(mhdc_batch b, int32_t wg_size);
+int mhdc_batch_get_info(mhdc_batch b, mhdc_batch_info *out);
+void mhdc_batch_destroy(mhdc_batch b);
+
+/* ------------------------------------------------------------ autotuner */
+typedef struct {
+    int32_t n_b;           /* chosen rows per block */
+    mhdc_launch launch;    /* chosen launch shape */
+    float us;              /* its mean time per call, microseconds */
+    int32_t tried;         /* (n_b, shape) pairs timed */
+} mhdc_tune_result;
+
+/* Convert for every candidate n_b (threshold fixed), time spmm with nrhs
+ * right-hand sides for each launch shape on `stream` with HIP events, and
+ * return the fastest handle (launch shape set) or NULL on error.  The
+ * paper gives only a policy range for bl (Sec. 6.4.3); this measures it.
+ * Synchronous; allocates and frees its own x/y scratch. */
+mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr,
+                          const int32_t *colind, const double *val,
+                          double threshold, int32_t nrhs,
+                          const int32_t *nb_candidates, int32_t n_candidates,
+                          hipStream_t stream, mhdc_tune_result *out);
+/* Time the batch under wg_size 64 and 256, keep the faster.  Runs the
+ * batch, so the bound Y blocks are overwritten.  Synchronous. */
+int mhdc_batch_tune(mhdc_batch b, hipStream_t stream, int32_t *best_wg,
+                    float *best_us);
+
 /* ------------------------------------------------------ failure injection */
 /* Test hook: the countdown-th device allocation made by the library from now
  * on fails with MHDC_ERR_OOM (0 disables).  Lets a host-side test drive every

@@ -8,22 +8,13 @@
 #include <cmath>
 #include <new>
 
-struct mhdc_s {
-    mhdc::BdcMatrix m;
-};
-struct hdc_s {
-    mhdc::BdcMatrix m;
-};
-struct csr_s {
-    mhdc::BdcMatrix m;
-};
-
 namespace mhdc {
 
 namespace {
 thread_local int t_code = MHDC_OK;
 thread_local std::string t_msg;
 std::atomic<int32_t> g_fail_countdown{0};
+}  // namespace
 
 mhdc_launch default_launch(int32_t n, int32_t n_b)
 {
@@ -38,6 +29,8 @@ mhdc_launch default_launch(int32_t n, int32_t n_b)
         return mhdc_launch{(one_block || n_b % 128 == 0) ? 2 : 1, 256, 0};
     return mhdc_launch{1, 64, 0};
 }
+
+namespace {
 
 void fill_info(const BdcMatrix &m, mhdc_info *o)
 {

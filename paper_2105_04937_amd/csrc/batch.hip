@@ -1,0 +1,334 @@
+// batch.hip -- many M-HDC / HDC / CSR products in one persistent launch.
+//
+// A batch holds up to thousands of (matrix, right-hand-side block) items of
+// uneven sizes.  The tiles of all items are numbered in one sequence; a
+// persistent grid sized to the machine (CUs x resident workgroups) takes
+// tiles from an atomic counter until the sequence is exhausted, so small
+// matrices never leave CUs idle the way one launch per matrix does.  Each
+// tile writes only its own rows (no floating-point atomics): the result of
+// every item is bit-identical to its single-matrix launch.
+//
+// The counter is cleared by a one-thread kernel launched just before the
+// persistent kernel (no memset node, so the pair can be captured in a HIP
+// graph and replayed).  Descriptors live in device memory, so rebinding X/Y
+// pointers takes effect in later replays without re-capture.
+#include "internal.h"
+#include "spmv_tile.h"
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+namespace mhdc {
+namespace {
+
+struct BatchItem {
+    SpmvArgs a;
+    int64_t tile_begin;  // first global tile number of this item
+    int32_t kc;          // accumulator width class (1, 2, 4, 8, 16)
+    int32_t pad;
+};
+
+template <int WG>
+constexpr int batch_lds_doubles()
+{
+    int m = 1;
+    m = std::max(m, 1 * TileShape<WG, 1>::CH);
+    m = std::max(m, 2 * TileShape<WG, 2>::CH);
+    m = std::max(m, 4 * TileShape<WG, 4>::CH);
+    m = std::max(m, 8 * TileShape<WG, 8>::CH);
+    m = std::max(m, 16 * TileShape<WG, 16>::CH);
+    return m;
+}
+
+__global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_batch(const BatchItem *__restrict__ items, int32_t count,
+                                              int64_t total_tiles, int32_t *counter)
+{
+    __shared__ double s_prod[batch_lds_doubles<WG>()];
+    __shared__ int64_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t t = s_tile;
+        __syncthreads();
+        if (t >= total_tiles)
+            break;  // the counter only grows: every workgroup reaches this
+        // item owning tile t: last item with tile_begin <= t
+        int32_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchItem &it = items[lo];
+        const int64_t local = t - it.tile_begin;
+        switch (it.kc) {
+        case 1: spmv_tile<WG, 1, 1, true>(it.a, local, s_prod); break;
+        case 2: spmv_tile<WG, 1, 2, true>(it.a, local, s_prod); break;
+        case 4: spmv_tile<WG, 1, 4, true>(it.a, local, s_prod); break;
+        case 8: spmv_tile<WG, 1, 8, true>(it.a, local, s_prod); break;
+        default: spmv_tile<WG, 1, 16, true>(it.a, local, s_prod); break;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace mhdc
+
+using namespace mhdc;
+
+struct mhdc_batch_s {
+    int32_t count = 0;
+    int32_t wg = 256;
+    int64_t total_tiles = 0;
+    int32_t grid = 0;
+    std::vector<const BdcMatrix *> mats;
+    std::vector<int32_t> nrhs;
+    std::vector<BatchItem> host_items;
+    BatchItem *d_items = nullptr;
+    int32_t *d_counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double flops = 0, bytes_alg = 0;
+};
+
+namespace {
+
+int batch_grid(int wg, int64_t total_tiles, int32_t *grid)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    MHDC_HIP_CHECK(hipGetDevice(&dev));
+    MHDC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (wg == 64)
+        MHDC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_batch<64>), 64, 0));
+    else
+        MHDC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_batch<256>), 256, 0));
+    int64_t g = (int64_t)cus * std::max(per_cu, 1);
+    if (g > total_tiles)
+        g = total_tiles;
+    *grid = (int32_t)std::max<int64_t>(g, 1);
+    return MHDC_OK;
+}
+
+// (Re)build the descriptor table for the current X/Y binding and workgroup
+// size and upload it.
+int upload_items(mhdc_batch_s *b, const double *const *X, const int64_t *ldx, double *const *Y,
+                 const int64_t *ldy)
+{
+    b->host_items.assign(b->count, BatchItem{});
+    int64_t tiles = 0;
+    double flops = 0, bytes = 0;
+    for (int32_t i = 0; i < b->count; i++) {
+        const BdcMatrix &m = *b->mats[i];
+        const int32_t k = b->nrhs[i];
+        const int64_t lx = ldx ? ldx[i] : m.n, ly = ldy ? ldy[i] : m.n;
+        int rc = check_operands(m, X[i], lx, Y[i], ly, k);
+        if (rc)
+            return rc;
+        BatchItem &it = b->host_items[i];
+        it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
+        it.kc = kc_for(k);
+        it.tile_begin = tiles;
+        tiles += ((int64_t)m.n + b->wg - 1) / b->wg;
+        flops += 2.0 * (double)m.nnz * k;
+        const double n = m.n;
+        double a_bytes;
+        if (m.kind == KIND_CSR)
+            a_bytes = 12.0 * (double)m.nnz + 4.0 * (n + 1);
+        else
+            a_bytes = 8.0 * (double)m.S + 4.0 * (double)m.K + 4.0 * ((double)m.n_blk + 1) +
+                      12.0 * (double)m.R + (m.R > 0 ? 4.0 * (n + 1) : 0.0);
+        bytes += a_bytes + 16.0 * n * k;
+    }
+    if (tiles > INT32_MAX)
+        return set_error(MHDC_ERR_SIZE, "too many tiles in the batch");
+    b->total_tiles = tiles;
+    b->flops = flops;
+    b->bytes_alg = bytes;
+    MHDC_HIP_CHECK(hipMemcpy(b->d_items, b->host_items.data(), sizeof(BatchItem) * b->count,
+                             hipMemcpyHostToDevice));
+    return batch_grid(b->wg, tiles, &b->grid);
+}
+
+int enqueue(mhdc_batch_s *b, hipStream_t s)
+{
+    if (b->total_tiles == 0)
+        return MHDC_OK;
+    k_batch_reset<<<1, 1, 0, s>>>(b->d_counter);
+    if (b->wg == 64)
+        k_batch<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+    else
+        k_batch<256><<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    return MHDC_OK;
+}
+
+void drop_graph(mhdc_batch_s *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats, const int32_t *nrhs,
+                             const double *const *X, const int64_t *ldx, double *const *Y,
+                             const int64_t *ldy, int32_t wg_size)
+{
+    clear_error();
+    if (count < 1 || !mats || !nrhs || !X || !Y) {
+        set_error(MHDC_ERR_INVALID_ARG, "count >= 1 and non-NULL mats, nrhs, X, Y required");
+        return nullptr;
+    }
+    if (wg_size != 64 && wg_size != 256) {
+        set_error(MHDC_ERR_NOT_SUPPORTED, "wg_size must be 64 or 256");
+        return nullptr;
+    }
+    mhdc_batch_s *b = new (std::nothrow) mhdc_batch_s;
+    if (!b) {
+        set_error(MHDC_ERR_OOM, "host allocation of the batch failed");
+        return nullptr;
+    }
+    b->count = count;
+    b->wg = wg_size;
+    for (int32_t i = 0; i < count; i++) {
+        if (!mats[i] || nrhs[i] < 1 || nrhs[i] > 16) {
+            set_error(MHDC_ERR_INVALID_ARG, "matrix handle NULL or nrhs outside [1, 16]");
+            delete b;
+            return nullptr;
+        }
+        b->mats.push_back(&mats[i]->m);
+        b->nrhs.push_back(nrhs[i]);
+    }
+    int rc = dmalloc((void **)&b->d_items, sizeof(BatchItem) * (size_t)count, "batch items");
+    if (!rc)
+        rc = dmalloc((void **)&b->d_counter, sizeof(int32_t), "batch counter");
+    if (!rc)
+        rc = upload_items(b, X, ldx, Y, ldy);
+    if (rc) {
+        dfree(b->d_items);
+        dfree(b->d_counter);
+        delete b;
+        return nullptr;
+    }
+    return b;
+}
+
+int mhdc_batch_bind(mhdc_batch b, const double *const *X, const int64_t *ldx, double *const *Y,
+                    const int64_t *ldy)
+{
+    clear_error();
+    if (!b || !X || !Y)
+        return set_error(MHDC_ERR_INVALID_ARG, "batch, X and Y must be non-NULL");
+    MHDC_HIP_CHECK(hipDeviceSynchronize());  // replays in flight read the table
+    const int32_t grid0 = b->grid;
+    int rc = upload_items(b, X, ldx, Y, ldy);
+    if (!rc && b->grid != grid0)
+        drop_graph(b);
+    return rc;
+}
+
+int mhdc_batch_run(mhdc_batch b, hipStream_t stream)
+{
+    clear_error();
+    if (!b)
+        return set_error(MHDC_ERR_INVALID_ARG, "batch is NULL");
+    return enqueue(b, stream);
+}
+
+int mhdc_batch_graph_launch(mhdc_batch b, hipStream_t stream)
+{
+    clear_error();
+    if (!b)
+        return set_error(MHDC_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->exec) {
+        hipStream_t cs = nullptr;
+        MHDC_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? enqueue(b, cs)
+                                 : set_error(MHDC_ERR_HIP, std::string("begin capture: ") +
+                                                               hipGetErrorString(e));
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (rc)
+            return rc;
+        if (e2 != hipSuccess)
+            return set_error(MHDC_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return set_error(MHDC_ERR_HIP, std::string("graph instantiate: ") +
+                                               hipGetErrorString(e));
+        }
+    }
+    MHDC_HIP_CHECK(hipGraphLaunch(b->exec, stream));
+    return MHDC_OK;
+}
+
+int mhdc_batch_set_wg(mhdc_batch b, int32_t wg_size)
+{
+    clear_error();
+    if (!b)
+        return set_error(MHDC_ERR_INVALID_ARG, "batch is NULL");
+    if (wg_size != 64 && wg_size != 256)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "wg_size must be 64 or 256");
+    if (wg_size == b->wg)
+        return MHDC_OK;
+    MHDC_HIP_CHECK(hipDeviceSynchronize());
+    std::vector<const double *> X(b->count);
+    std::vector<double *> Y(b->count);
+    std::vector<int64_t> lx(b->count), ly(b->count);
+    for (int32_t i = 0; i < b->count; i++) {
+        X[i] = b->host_items[i].a.X;
+        Y[i] = b->host_items[i].a.Y;
+        lx[i] = b->host_items[i].a.ldx;
+        ly[i] = b->host_items[i].a.ldy;
+    }
+    b->wg = wg_size;
+    drop_graph(b);
+    return upload_items(b, X.data(), lx.data(), Y.data(), ly.data());
+}
+
+int mhdc_batch_get_info(mhdc_batch b, mhdc_batch_info *out)
+{
+    clear_error();
+    if (!b || !out)
+        return set_error(MHDC_ERR_INVALID_ARG, "batch or out is NULL");
+    out->count = b->count;
+    out->wg_size = b->wg;
+    out->total_tiles = b->total_tiles;
+    out->grid = b->grid;
+    out->flops = b->flops;
+    out->bytes_alg = b->bytes_alg;
+    return MHDC_OK;
+}
+
+void mhdc_batch_destroy(mhdc_batch b)
+{
+    if (!b)
+        return;
+    drop_graph(b);
+    dfree(b->d_items);
+    dfree(b->d_counter);
+    delete b;
+}
+
+}  // extern "C"

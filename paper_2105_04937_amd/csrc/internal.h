@@ -63,6 +63,8 @@ void free_matrix(BdcMatrix &m);
 
 // spmv.hip
 struct SpmvArgs;
+SpmvArgs make_args(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                   int32_t k, int32_t v);
 int kc_for(int k);
 int check_operands(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
                    int64_t ldy, int32_t k);
@@ -75,4 +77,18 @@ int check_launch(const mhdc_launch &cfg);
 int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
                        int64_t *total, hipStream_t stream);
 
+// api.hip: handle creation shared with the autotuner
+mhdc_launch default_launch(int32_t n, int32_t n_b);
+
 }  // namespace mhdc
+
+// The opaque handle types of the C-ABI: each wraps one BdcMatrix.
+struct mhdc_s {
+    mhdc::BdcMatrix m;
+};
+struct hdc_s {
+    mhdc::BdcMatrix m;
+};
+struct csr_s {
+    mhdc::BdcMatrix m;
+};

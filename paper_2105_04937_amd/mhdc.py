@@ -45,6 +45,20 @@ class Launch(ctypes.Structure):
                 ("xcd_remap", ctypes.c_int32)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("total_tiles", ctypes.c_int64), ("grid", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("bytes_alg", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("n_b", ctypes.c_int32), ("launch", Launch), ("us", ctypes.c_float),
+                ("tried", ctypes.c_int32)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -80,6 +94,17 @@ SIGNATURES = {
     "mhdc_stream_direct": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp]),
     "mhdc_stream_indirect": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp, _vp]),
     "mhdc_debug_fail_alloc": (ctypes.c_int, [_i32]),
+    "mhdc_batch_create": (_vp, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
+    "mhdc_batch_bind": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mhdc_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "mhdc_batch_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "mhdc_batch_set_wg": (ctypes.c_int, [_vp, _i32]),
+    "mhdc_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(BatchInfo)]),
+    "mhdc_batch_destroy": (None, [_vp]),
+    "mhdc_autotune": (_vp, [_i32, _vp, _vp, _vp, _f64, _i32, _vp, _i32, _vp,
+                            ctypes.POINTER(TuneResult)]),
+    "mhdc_batch_tune": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i32),
+                                       ctypes.POINTER(ctypes.c_float)]),
 }
 
 
@@ -279,6 +304,93 @@ class CSRMatrix(_Matrix):
         if not h:
             _raise()
         return cls(h, n)
+
+
+def autotune(rowptr, colind, val, theta: float, nrhs: int = 1,
+             nb_candidates=(32, 64, 128, 256, 512), stream=None):
+    """Convert for each candidate n_b, time every launch shape, return
+    (fastest MHDCMatrix, result dict)."""
+    n, rp, ci, v = _csr_args(rowptr, colind, val)
+    cands = (ctypes.c_int32 * len(nb_candidates))(*nb_candidates)
+    res = TuneResult()
+    h = lib().mhdc_autotune(n, rp, ci, v, float(theta), int(nrhs), cands, len(nb_candidates),
+                            _stream(stream), ctypes.byref(res))
+    if not h:
+        _raise()
+    out = dict(n_b=res.n_b, us=res.us, tried=res.tried,
+               launch=(res.launch.rows_per_lane, res.launch.wg_size, res.launch.xcd_remap))
+    return MHDCMatrix(h, n), out
+
+
+class Batch:
+    """Several M-HDC products Y_i = A_i X_i in one persistent launch.
+
+    mats: MHDCMatrix list; Xs: per item a (k_i, n_i) float64 device tensor
+    (rows are right-hand sides); Ys: outputs of the same shapes (allocated
+    when None).  The tensors must stay alive while the batch is used."""
+
+    def __init__(self, mats, Xs, Ys=None, wg_size=256):
+        self.mats = list(mats)
+        self.Xs = list(Xs)
+        self.Ys = list(Ys) if Ys is not None else [torch.empty_like(X) for X in self.Xs]
+        cnt = len(self.mats)
+        hs = (ctypes.c_void_p * cnt)(*[m._h for m in self.mats])
+        k = (ctypes.c_int32 * cnt)(*[X.shape[0] for X in self.Xs])
+        xp, yp, lx, ly = self._ptrs()
+        torch.cuda.synchronize()
+        self._h = lib().mhdc_batch_create(cnt, hs, k, xp, lx, yp, ly, int(wg_size))
+        if not self._h:
+            _raise()
+
+    def _ptrs(self):
+        cnt = len(self.mats)
+        for m, X, Y in zip(self.mats, self.Xs, self.Ys):
+            if X.dim() != 2 or X.shape[1] != m.n or Y.shape != X.shape:
+                raise ValueError("X_i, Y_i must have shape (k_i, n_i)")
+            _dptr(X, torch.float64, "X")
+            _dptr(Y, torch.float64, "Y")
+        xp = (ctypes.c_void_p * cnt)(*[X.data_ptr() for X in self.Xs])
+        yp = (ctypes.c_void_p * cnt)(*[Y.data_ptr() for Y in self.Ys])
+        lx = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
+        ly = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
+        return xp, yp, lx, ly
+
+    def bind(self, Xs, Ys):
+        self.Xs, self.Ys = list(Xs), list(Ys)
+        xp, yp, lx, ly = self._ptrs()
+        _check(lib().mhdc_batch_bind(self._h, xp, lx, yp, ly))
+
+    def run(self, stream=None):
+        _check(lib().mhdc_batch_run(self._h, _stream(stream)))
+        return self.Ys
+
+    def graph_launch(self, stream=None):
+        _check(lib().mhdc_batch_graph_launch(self._h, _stream(stream)))
+        return self.Ys
+
+    def set_wg(self, wg_size):
+        _check(lib().mhdc_batch_set_wg(self._h, int(wg_size)))
+
+    def tune(self, stream=None):
+        wg, us = ctypes.c_int32(0), ctypes.c_float(0)
+        _check(lib().mhdc_batch_tune(self._h, _stream(stream), ctypes.byref(wg), ctypes.byref(us)))
+        return wg.value, us.value
+
+    def info(self):
+        out = BatchInfo()
+        _check(lib().mhdc_batch_get_info(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().mhdc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stream_direct(A, B, C, stream=None):

@@ -1,0 +1,134 @@
+"""Batched persistent launch, HIP-graph replay and the autotuner, through the
+C-ABI.  Every item of a batch must equal its single-matrix launch bit for bit
+and the oracle's sequential M-HDC kernel (Fig. 16) bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_04937_amd import mhdc, synth
+from tests.gpu_helpers import assert_oracle_bits, assert_same_bits, assert_spmv_close, dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _items():
+    """Mixed workload: batch members (7/19/27-point, drops, k = 1..16), a
+    matrix without remainder, one with only a remainder, a tiny one, one
+    with a ragged last block."""
+    out = []
+    for i in (0, 1, 2, 3, 5, 8):
+        m, k = synth.batch_member(i)
+        out.append((m, k, [64, 128, 32, 256, 64, 48][len(out) % 6]))
+    out.append((synth.laplacian7(20), 3, 400))            # R = 0
+    out.append((synth.random_csr(300, 5, density=0.02), 2, 64))  # mostly remainder
+    out.append((synth.random_csr(5, 6, density=0.5, bands=[0]), 16, 4))
+    out.append((synth.partially_diagonal(13, 7), 9, 100))  # 2197 rows, ragged last block
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch_case():
+    items = _items()
+    say("batch: %d items, rows %s" % (len(items), [m.n for m, _, _ in items]))
+    mats, Xs, refs, devs = [], [], [], []
+    for j, (m, k, nb) in enumerate(items):
+        d = dev(m)
+        devs.append(d)
+        mats.append(mhdc.MHDCMatrix.from_csr(*d, nb, 0.6))
+        X = np.ascontiguousarray(np.random.default_rng(100 + j).uniform(-1, 1, size=(k, m.n)))
+        Xs.append(torch.from_numpy(X).cuda())
+        refs.append(oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, nb, 0.6))
+    return items, mats, Xs, refs, devs
+
+
+def _check_items(items, mats, Xs, Ys, refs):
+    torch.cuda.synchronize()
+    for (m, k, nb), mat, X, Y, ref in zip(items, mats, Xs, Ys, refs):
+        Xh = X.cpu().numpy()
+        Yh = Y.cpu().numpy()
+        single = mat.spmm(X).cpu().numpy()
+        assert_same_bits(Yh, single, "batch item n=%d vs single launch" % m.n)
+        for r in range(k):
+            assert_oracle_bits(Yh[r], oracle.mhdc_spmv(ref, Xh[r]), "item n=%d rhs %d" % (m.n, r))
+            assert_spmv_close(Yh[r], m, Xh[r])
+
+
+def test_batch_run_matches_items(batch_case):
+    items, mats, Xs, refs, _ = batch_case
+    for wg in (256, 64):
+        say("case: batch run wg=%d" % wg)
+        b = mhdc.Batch(mats, Xs, wg_size=wg)
+        inf = b.info()
+        assert inf["count"] == len(items) and inf["grid"] >= 1
+        assert inf["total_tiles"] == sum((m.n + wg - 1) // wg for m, _, _ in items)
+        b.run()
+        _check_items(items, mats, Xs, b.Ys, refs)
+        b.close()
+
+
+def test_batch_graph_replays(batch_case):
+    """Replay the captured graph several times with eager work in between;
+    every replay must equal the eager batch result for the current X."""
+    items, mats, Xs0, refs, _ = batch_case
+    say("case: batch graph replays")
+    Xs = [X.clone() for X in Xs0]
+    b = mhdc.Batch(mats, Xs)
+    stream = torch.cuda.Stream()
+    for rep in range(4):
+        with torch.cuda.stream(stream):
+            for X in Xs:
+                X.mul_(-1.25).add_(0.125)  # eager work on the same stream
+            b.graph_launch(stream)
+        stream.synchronize()
+        got = [Y.clone() for Y in b.Ys]
+        b.run()
+        torch.cuda.synchronize()
+        for g, Y in zip(got, b.Ys):
+            assert_same_bits(g.cpu().numpy(), Y.cpu().numpy(), "replay %d" % rep)
+    _check_items(items, mats, Xs, b.Ys, refs)
+    # rebind to fresh tensors: the graph reads the new table
+    Xs2 = [torch.flip(X, dims=[1]).contiguous() for X in Xs]
+    Ys2 = [torch.empty_like(X) for X in Xs2]
+    b.bind(Xs2, Ys2)
+    b.graph_launch()
+    _check_items(items, mats, Xs2, Ys2, refs)
+    b.close()
+
+
+def test_batch_tune_and_errors(batch_case):
+    items, mats, Xs, refs, _ = batch_case
+    say("case: batch tune + errors")
+    b = mhdc.Batch(mats, Xs)
+    wg, us = b.tune()
+    assert wg in (64, 256) and us > 0
+    b.run()
+    _check_items(items, mats, Xs, b.Ys, refs)
+    b.close()
+    bad = [torch.zeros((17, mats[0].n), dtype=torch.float64, device="cuda")] + Xs[1:]
+    with pytest.raises(ValueError):
+        mhdc.Batch(mats, bad[:1] + Xs[1:], Ys=[torch.zeros(1, device="cuda")] + Xs[1:])
+    with pytest.raises(mhdc.MhdcError) as e:
+        mhdc.Batch(mats, bad)
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    with pytest.raises(mhdc.MhdcError) as e:   # Y_i aliases X_i
+        mhdc.Batch(mats, Xs, Ys=Xs)
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_autotune(k):
+    m = synth.partially_diagonal(40, 17, drop=0.15)
+    say("case: autotune n=%d k=%d" % (m.n, k))
+    d = dev(m)
+    cands = (32, 64, 128, 256)
+    h, res = mhdc.autotune(*d, 0.6, nrhs=k, nb_candidates=cands)
+    assert res["n_b"] in cands and res["tried"] >= len(cands) * 3 and res["us"] > 0
+    inf = h.info()
+    assert inf["n_b"] == res["n_b"]
+    assert (inf["rows_per_lane"], inf["wg_size"], inf["xcd_remap"]) == res["launch"]
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, res["n_b"], 0.6)
+    X = np.ascontiguousarray(np.random.default_rng(k).uniform(-1, 1, size=(k, m.n)))
+    Y = h.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
+    for r in range(k):
+        assert_oracle_bits(Y[r], oracle.mhdc_spmv(ref, X[r]), "autotuned rhs %d" % r)
