@@ -1,0 +1,98 @@
+"""Pins of the selector oracle: the census features against a brute-force
+count over dense diagonals and closed forms, backpropagation against
+central finite differences in FP64, Adam against its first-step closed form."""
+import numpy as np
+import pytest
+
+from oracle import selector as S
+from paper_2105_04937_amd import synth
+
+
+def test_param_count():
+    assert S.N_PARAMS == 66 * 128 + 128 + 128 * 128 + 128 + 128 * 2 + 2 == 25_346
+
+
+def test_offset_bins():
+    d = np.array([0, 1, 2, 3, 4, 7, 8, -1, -2, -3, -4, 2**30, -(2**30), 2**31 - 1, 5, -6])
+    want = [32, 33, 34, 34, 35, 35, 36, 31, 30, 30, 29, 63, 1, 63, 35, 29]
+    assert list(S.offset_bin(d)) == want
+    a = np.array([1, 2, 3, 4, 2**20 - 1, 2**20, 2**30 + 5])
+    assert list(S.floor_log2(a)) == [0, 1, 1, 2, 19, 20, 30]
+
+
+def _brute(A, nb):
+    n = A.shape[0]
+    nnz_stored = None
+    f = np.zeros(S.N_IN)
+    n_blk = (n + nb - 1) // nb
+    for ib in range(n_blk):
+        r0, r1 = ib * nb, min(n, ib * nb + nb)
+        for d in range(-(n - 1), n):
+            cnt = sum(1 for i in range(r0, r1) if 0 <= i + d < n and A[i, i + d] != 0)
+            if cnt:
+                if d == 0:
+                    b = 32
+                else:
+                    k = abs(d).bit_length() - 1
+                    b = 33 + min(k, 30) if d > 0 else 31 - min(k, 31)
+                f[b] += cnt * cnt / (r1 - r0)
+    return f, nnz_stored
+
+
+@pytest.mark.parametrize("n,nb", [(40, 8), (33, 7), (64, 64), (20, 256)])
+def test_features_brute_force(n, nb):
+    m = synth.random_csr(n, n + nb, density=0.1, bands=[0, 1, -3, 9], zero_frac=0.1)
+    A = synth.dense_of(m)
+    f = S.features(m.rowptr, m.colind, m.val, probe_nb=nb)
+    raw, _ = _brute(A, nb)
+    assert np.allclose(f[:64], (raw[:64] / m.nnz).astype(np.float32), rtol=1e-6, atol=0)
+    assert f[64] == np.float32(np.log2(n) / 32)
+    assert f[65] == np.float32(np.log2(m.nnz) / 32)
+
+
+def test_features_closed_forms():
+    # identity: one full diagonal per block -> f[32] = 1
+    n = 700
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    f = S.features(rp, ci, np.ones(n))
+    assert f[32] == 1.0 and f[:64].sum() == 1.0
+    # 7-point grid with bl = N = 256: the bins of +-1, +-256, +-65536 and 0
+    # hold full (or one-short) partial diagonals; their total is close to 1
+    m = synth.laplacian7(16)
+    f = S.features(m.rowptr, m.colind, m.val, probe_nb=256)
+    assert 0.9 < f[:64].sum() <= 1.0
+    want = {int(S.offset_bin(d)) for d in (0, 1, -1, 16, -16, 256, -256)}
+    assert set(int(b) for b in np.nonzero(f[:64])[0]) == want
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    p = S.init_params(1).astype(np.float64) + rng.normal(0, 0.01, S.N_PARAMS)
+    X = rng.uniform(0, 1, size=(7, S.N_IN))
+    T = rng.normal(size=(7, 2))
+    L, g = S.loss_and_grad(p, X, T, w=(1.0, 0.25))
+    idx = rng.choice(S.N_PARAMS, size=300, replace=False)
+    idx = np.concatenate([idx, [S.N_PARAMS - 1, S.N_PARAMS - 2, S.N_PARAMS - 130, 0]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(S.N_PARAMS)
+        e[i] = h
+        Lp, _ = S.loss_and_grad(p + e, X, T, w=(1.0, 0.25))
+        Lm, _ = S.loss_and_grad(p - e, X, T, w=(1.0, 0.25))
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(2)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    p1, m, v = S.adam(p, g, np.zeros(50), np.zeros(50), 1, lr=0.01, eps=0.0)
+    assert np.allclose(p1, p - 0.01 * np.sign(g), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_decode():
+    th, nb = S.decode([[0.3, 4.2], [0.72, 7.6], [1.5, 20.0]])
+    assert list(th) == [0.5, 0.72, 0.9] and list(nb) == [32, 256, 4096]
