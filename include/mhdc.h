@@ -251,6 +251,69 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr,
 int mhdc_batch_tune(mhdc_batch b, hipStream_t stream, int32_t *best_wg,
                     float *best_us);
 
+/* ----------------------------------------------------- learned selector */
+/* The paper fixes neither theta nor bl: it proposes a policy (50 <~ bl <~
+ * 500, theta = 0.6; Sec. 6.4.3) and leaves the decision open (Sec. 7).  A
+ * small network proposes (theta, n_b) from a census of the matrix; the
+ * paper's byte model (V = V_A + V_x + V_y, Eqs. 24/34) judges the proposal
+ * against the policy (theta = 0.6, n_b = 256), which is also the fallback.
+ *
+ * Features: 66 floats.  f[b], b < 64 = (sum over block ib, offset d in bin
+ * b of N~(d,ib)^2 / rows_ib) / nnz with N~ counted at block size 256 (Sec.
+ * 4.3's count) and bin b = 32 for d = 0, 33 + min(floor(log2 d), 30) for
+ * d > 0, 31 - min(floor(log2 -d), 31) for d < 0; f[64] = log2(n)/32,
+ * f[65] = log2(nnz)/32.  `feat` is a device array of 66 floats.
+ * Synchronous. */
+int mhdc_features(int32_t n, const int32_t *rowptr, const int32_t *colind,
+                  const double *val, float *feat, hipStream_t stream);
+
+/* Network: 66 -> 128 -> 128 -> 2, ReLU hidden layers, FP32.  Parameters
+ * (MHDC_MLP_PARAMS floats) in the order W1 (128x66), b1, W2 (128x128), b2,
+ * W3 (2x128), b3, row-major.  Output o = (theta, log2 n_b). */
+#define MHDC_MLP_PARAMS 25346
+typedef struct mhdc_mlp_s *mhdc_mlp;
+/* params_host: HOST array of initial parameters (the caller draws them). */
+mhdc_mlp mhdc_mlp_create(const float *params_host);
+/* Copy the current parameters to a HOST array (synchronous). */
+int mhdc_mlp_get_params(mhdc_mlp m, float *params_host);
+/* out[B][2] = network(X[B][66]); device arrays; asynchronous on stream. */
+int mhdc_mlp_forward(mhdc_mlp m, const float *X, int32_t B, float *out,
+                     hipStream_t stream);
+/* loss = sum_r (w0 (o_r0 - T_r0)^2 + w1 (o_r1 - T_r1)^2) / B and its
+ * gradient (MHDC_MLP_PARAMS floats, parameter order) by backpropagation;
+ * device arrays; asynchronous on stream. */
+int mhdc_mlp_loss_grad(mhdc_mlp m, const float *X, const float *T, int32_t B,
+                       float w0, float w1, float *loss, float *grad,
+                       hipStream_t stream);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) on
+ * minibatches of B rows: step s uses rows order[s*B .. s*B+B) of X[N][66]
+ * and targets T[N][2] (device arrays; the caller draws the order).
+ * loss_hist[s] receives each step's loss.  One step is captured once as a
+ * HIP graph and replayed.  Synchronous. */
+int mhdc_mlp_train(mhdc_mlp m, const float *X, const float *T, int32_t N,
+                   const int32_t *order, int64_t steps, int32_t B, float lr,
+                   float w0, float w1, float *loss_hist, hipStream_t stream);
+void mhdc_mlp_destroy(mhdc_mlp m);
+
+typedef struct {
+    double theta;          /* chosen threshold */
+    int32_t n_b;           /* chosen rows per block */
+    int32_t used_rule;     /* 1 if the policy (0.6, 256) was used */
+    double theta_net;      /* the network's proposal (theta snapped to 0.1) */
+    int32_t n_b_net;
+    int32_t net_ok;        /* 0 if the network gave a non-finite output */
+    double bytes_net;      /* model volume V of the proposal */
+    double bytes_rule;     /* model volume V of the policy */
+} mhdc_select_result;
+
+/* Choose (theta, n_b) and convert.  model = NULL uses the policy.  The
+ * proposal is kept unless its V exceeds (1 + tolerance) x the policy's V.
+ * Returns the M-HDC handle of the choice, NULL on error.  Synchronous. */
+mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr,
+                        const int32_t *colind, const double *val,
+                        mhdc_mlp model, double tolerance,
+                        mhdc_select_result *out);
+
 /* ------------------------------------------------------ failure injection */
 /* Test hook: the countdown-th device allocation made by the library from now
  * on fails with MHDC_ERR_OOM (0 disables).  Lets a host-side test drive every

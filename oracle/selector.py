@@ -155,9 +155,10 @@ def adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def decode(out):
-    """Network output -> (theta, n_b): theta = clip(o0, 0.5, 0.9),
-    n_b = 2 ** clip(round(o1), 5, 12)."""
+    """Network output -> (theta, n_b): theta = round(10 clip(o0, 0.5, 0.9))/10
+    (the theta grid of Sec. 6.4.1), n_b = 2 ** clip(round(o1), 5, 12);
+    rounding half to even on both."""
     out = np.atleast_2d(np.asarray(out, np.float64))
-    theta = np.clip(out[:, 0], 0.5, 0.9)
+    theta = np.round(np.clip(out[:, 0], 0.5, 0.9) * 10.0) / 10.0
     nb = 2 ** np.clip(np.round(out[:, 1]), 5, 12).astype(np.int64)
     return theta, nb

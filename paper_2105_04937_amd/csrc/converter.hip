@@ -15,6 +15,7 @@
 // HDC counts N(d) over the whole matrix (per-chunk tables flushed into one
 // dense count array), keeps d with N(d)/n >= theta by an order-preserving
 // compaction, and is then laid out as one block of n rows.
+#include "census.h"
 #include "internal.h"
 
 #include <climits>
@@ -23,10 +24,8 @@
 namespace mhdc {
 namespace {
 
-constexpr int CV_WG = 256;
-constexpr int CENSUS_LDS_SLOTS = 8192;      // LDS hash capacity (64 KB)
+constexpr int CV_WG = CENSUS_WG;
 constexpr int HDC_CENSUS_ROWS = 256;        // rows per HDC census chunk
-constexpr int32_t EMPTY_KEY = INT32_MIN;    // offsets lie in [-(n-1), n-1]
 
 inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 22)
 {
@@ -78,26 +77,6 @@ __global__ __launch_bounds__(CV_WG) void k_block_max(int32_t n, int32_t n_b, int
 }
 
 // ---------------------------------------------------------------- census
-__device__ inline uint32_t key_hash(int32_t d, uint32_t cap)
-{
-    return ((uint32_t)d * 2654435761u) % cap;
-}
-
-// Count one occurrence of key d.  The table has more slots than distinct
-// keys can occur (cap > entries of the block), so probing terminates.
-__device__ inline void table_add(int32_t *keys, int32_t *cnts, uint32_t cap, int32_t d)
-{
-    uint32_t h = key_hash(d, cap);
-    for (;;) {
-        int32_t prev = atomicCAS(&keys[h], EMPTY_KEY, d);
-        if (prev == EMPTY_KEY || prev == d) {
-            atomicAdd(&cnts[h], 1);
-            return;
-        }
-        h = (h + 1 == cap) ? 0 : h + 1;
-    }
-}
-
 // mode 0 (M-HDC): per block, select and sort the kept offsets:
 //   Kb[ib] = number kept, sel_tmp[e0 .. e0+Kb) = kept offsets ascending,
 //   with e0 = rowptr[ib*n_b] (a block keeps at most its entry count).
@@ -118,37 +97,12 @@ __global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n
         const int64_t r0 = ib * n_b, r1 = min((int64_t)n, r0 + n_b);
         const int64_t rows = r1 - r0;
         const int64_t e0 = rowptr[r0], e1 = rowptr[r1];
-        const int64_t m = e1 - e0;
 
-        int32_t *keys, *cnts;
-        uint32_t cap;
-        if (m < CENSUS_LDS_SLOTS) {
-            keys = s_keys;
-            cnts = s_cnts;
-            uint32_t c = 64;
-            while (c < 2 * (uint32_t)m && c < CENSUS_LDS_SLOTS)
-                c <<= 1;
-            cap = c > (uint32_t)m ? c : (uint32_t)CENSUS_LDS_SLOTS;
-        } else {
-            keys = gkeys + 2 * e0;
-            cnts = gcnts + 2 * e0;
-            cap = (uint32_t)(2 * m);
-        }
-        for (uint32_t s = threadIdx.x; s < cap; s += CV_WG) {
-            keys[s] = EMPTY_KEY;
-            cnts[s] = 0;
-        }
         if (threadIdx.x == 0)
             s_nsel = 0;
-        __syncthreads();
-
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += CV_WG) {
-            const int32_t a = rowptr[i], b = rowptr[i + 1];
-            for (int32_t k = a; k < b; k++)
-                if (val[k] != 0.0)
-                    table_add(keys, cnts, cap, colind[k] - (int32_t)i);
-        }
-        __syncthreads();
+        int32_t *keys, *cnts;
+        const uint32_t cap = census_block(r0, r1, e0, e1, rowptr, colind, val, s_keys, s_cnts,
+                                          gkeys, gcnts, &keys, &cnts);
 
         for (uint32_t s = threadIdx.x; s < cap; s += CV_WG) {
             const int32_t key = keys[s];

@@ -1,0 +1,600 @@
+// selector.hip -- learned choice of (theta, n_b) for M-HDC.
+//
+// The paper fixes neither parameter; it gives a policy (50 <~ bl <~ 500,
+// theta = 0.6) and notes that the CSR rate, computable in advance, drives
+// performance (Sec. 6.4.3), and leaves open how to decide M-HDC's use
+// (Sec. 7).  Here a small network reads a census of the matrix and proposes
+// (theta, n_b); the paper's byte model (V of Eqs. 24/34, the basis of the
+// relative performance of Eq. 28) judges the proposal against the policy
+// and the policy is the fallback.
+//
+// Features (66, FP32): census of nonzeros per (block, offset) at probe
+// block size 256 (the N~(d, ib) of Sec. 4.3); per offset bin b (sign and
+// floor(log2|d|)) f[b] = sum N~^2 / rows_ib / nnz, then log2(n)/32 and
+// log2(nnz)/32.  The sums are exact 64-bit integers split into full blocks
+// and the last block, finished in FP64.
+//
+// Network: 66 -> 128 -> 128 -> 2, ReLU hidden layers, FP32 parameters in
+// one vector (W1 128x66, b1, W2 128x128, b2, W3 2x128, b3, row-major).
+// Every reduction (over inputs in the forward pass, over the minibatch in
+// the weight gradients) runs in a fixed order in one thread, so training is
+// deterministic.  One training step (minibatch gather, forward, loss,
+// backward, Adam, step counter) is captured once as a HIP graph and
+// replayed; the step counter lives in device memory.  The layers are tiny
+// (at most 128x128 per sample); each launch is latency-bound, not a job
+// for the matrix cores.
+#include "census.h"
+#include "internal.h"
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+namespace mhdc {
+namespace {
+
+constexpr int N_BINS = 64, N_IN = 66, HID = 128, N_OUT = 2, PROBE_NB = 256;
+constexpr int P_W1 = 0;
+constexpr int P_B1 = P_W1 + HID * N_IN;
+constexpr int P_W2 = P_B1 + HID;
+constexpr int P_B2 = P_W2 + HID * HID;
+constexpr int P_W3 = P_B2 + HID;
+constexpr int P_B3 = P_W3 + N_OUT * HID;
+constexpr int N_PARAMS = P_B3 + N_OUT;
+static_assert(N_PARAMS == 25346, "parameter layout");
+constexpr int TW = 256;
+
+inline unsigned blocks_for(int64_t items) { return (unsigned)((items + TW - 1) / TW); }
+
+// ------------------------------------------------------------- features
+__device__ inline int offset_bin(int32_t d)
+{
+    if (d == 0)
+        return 32;
+    const uint32_t a = d > 0 ? (uint32_t)d : (uint32_t)(-(int64_t)d);
+    const int k = 31 - __clz(a);
+    return d > 0 ? 33 + min(k, 30) : 31 - min(k, 31);
+}
+
+__global__ __launch_bounds__(CENSUS_WG) void k_feat_census(
+    int32_t n, int64_t n_blk, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ colind, const double *__restrict__ val, int32_t *gkeys,
+    int32_t *gcnts, unsigned long long *sums)
+{
+    __shared__ int32_t s_keys[CENSUS_LDS_SLOTS];
+    __shared__ int32_t s_cnts[CENSUS_LDS_SLOTS];
+    __shared__ unsigned long long s_sum[2 * N_BINS];  // [0,64) full blocks, [64,128) last
+    for (int t = threadIdx.x; t < 2 * N_BINS; t += CENSUS_WG)
+        s_sum[t] = 0;
+    for (int64_t ib = blockIdx.x; ib < n_blk; ib += gridDim.x) {
+        const int64_t r0 = ib * PROBE_NB, r1 = min((int64_t)n, r0 + PROBE_NB);
+        int32_t *keys, *cnts;
+        const uint32_t cap = census_block(r0, r1, rowptr[r0], rowptr[r1], rowptr, colind, val,
+                                          s_keys, s_cnts, gkeys, gcnts, &keys, &cnts);
+        const int base = ib == n_blk - 1 ? N_BINS : 0;
+        for (uint32_t s = threadIdx.x; s < cap; s += CENSUS_WG) {
+            const int32_t key = keys[s];
+            if (key != EMPTY_KEY) {
+                const unsigned long long c = (unsigned long long)cnts[s];
+                atomicAdd(&s_sum[base + offset_bin(key)], c * c);
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < 2 * N_BINS; t += CENSUS_WG)
+        if (s_sum[t])
+            atomicAdd(&sums[t], s_sum[t]);
+}
+
+__global__ void k_feat_finish(int32_t n, int64_t nnz, int64_t n_blk,
+                              const unsigned long long *__restrict__ sums, float *feat)
+{
+    const int b = threadIdx.x;
+    const double rows_last = (double)(n - (n_blk - 1) * PROBE_NB);
+    if (b < N_BINS) {
+        double f = 0.0;
+        if (nnz > 0)
+            f = ((double)sums[b] / (double)PROBE_NB + (double)sums[N_BINS + b] / rows_last) /
+                (double)nnz;
+        feat[b] = (float)f;
+    } else if (b == N_BINS) {
+        feat[b] = (float)(log2((double)n) / 32.0);
+    } else if (b == N_BINS + 1) {
+        feat[b] = nnz > 0 ? (float)(log2((double)nnz) / 32.0) : 0.0f;
+    }
+}
+
+// ------------------------------------------------------------- network
+// out[r][j] = act(b[j] + sum_i W[j][i] * in[r][i]), i ascending
+__global__ __launch_bounds__(TW) void k_dense_fwd(const float *__restrict__ in, int in_dim,
+                                                  const float *__restrict__ W,
+                                                  const float *__restrict__ b, int out_dim,
+                                                  float *__restrict__ out, int B, int relu)
+{
+    const int idx = blockIdx.x * TW + threadIdx.x;
+    if (idx >= B * out_dim)
+        return;
+    const int r = idx / out_dim, j = idx - r * out_dim;
+    const float *w = W + (int64_t)j * in_dim;
+    const float *x = in + (int64_t)r * in_dim;
+    float s = b[j];
+    for (int i = 0; i < in_dim; i++)
+        s += w[i] * x[i];
+    out[idx] = relu ? fmaxf(s, 0.0f) : s;
+}
+
+// loss = sum_r sum_o w_o (out - T)^2 / B (fixed-order tree), d_out = 2 w (out - T) / B.
+// One workgroup.  loss_at: destination of the loss; with step != nullptr the
+// loss goes to loss_at[*local_step].
+__global__ __launch_bounds__(TW) void k_loss_grad(const float *__restrict__ out,
+                                                  const float *__restrict__ T, int B, float w0,
+                                                  float w1, float *__restrict__ d_out,
+                                                  float *loss_at, const int32_t *local_step)
+{
+    __shared__ float part[TW];
+    float acc = 0.0f;
+    for (int idx = threadIdx.x; idx < B * N_OUT; idx += TW) {
+        const float w = (idx % N_OUT) == 0 ? w0 : w1;
+        const float d = out[idx] - T[idx];
+        d_out[idx] = 2.0f * w * d / (float)B;
+        acc += w * d * d;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = TW / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float *dst = loss_at + (local_step ? *local_step : 0);
+        *dst = part[0] / (float)B;
+    }
+}
+
+// gW[j][i] = sum_r d_out[r][j] * in[r][i];  gb[j] = sum_r d_out[r][j]
+__global__ __launch_bounds__(TW) void k_dense_bwd_w(const float *__restrict__ d_out,
+                                                    const float *__restrict__ in, int B,
+                                                    int in_dim, int out_dim,
+                                                    float *__restrict__ gW,
+                                                    float *__restrict__ gb)
+{
+    const int idx = blockIdx.x * TW + threadIdx.x;
+    if (idx >= out_dim * (in_dim + 1))
+        return;
+    const int j = idx / (in_dim + 1), i = idx - j * (in_dim + 1);
+    float s = 0.0f;
+    if (i < in_dim) {
+        for (int r = 0; r < B; r++)
+            s += d_out[(int64_t)r * out_dim + j] * in[(int64_t)r * in_dim + i];
+        gW[(int64_t)j * in_dim + i] = s;
+    } else {
+        for (int r = 0; r < B; r++)
+            s += d_out[(int64_t)r * out_dim + j];
+        gb[j] = s;
+    }
+}
+
+// d_in[r][i] = (sum_j d_out[r][j] W[j][i]) * [h[r][i] > 0]   (h = ReLU output)
+__global__ __launch_bounds__(TW) void k_dense_bwd_x(const float *__restrict__ d_out,
+                                                    const float *__restrict__ W,
+                                                    const float *__restrict__ h, int B,
+                                                    int in_dim, int out_dim,
+                                                    float *__restrict__ d_in)
+{
+    const int idx = blockIdx.x * TW + threadIdx.x;
+    if (idx >= B * in_dim)
+        return;
+    const int r = idx / in_dim, i = idx - r * in_dim;
+    float s = 0.0f;
+    for (int j = 0; j < out_dim; j++)
+        s += d_out[(int64_t)r * out_dim + j] * W[(int64_t)j * in_dim + i];
+    d_in[idx] = h[idx] > 0.0f ? s : 0.0f;
+}
+
+// Adam at step t = *step + 1 (Kingma & Ba, bias-corrected moments)
+__global__ __launch_bounds__(TW) void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                             float *__restrict__ m, float *__restrict__ v,
+                                             int P, float lr, float b1, float b2, float eps,
+                                             const int32_t *step)
+{
+    const int idx = blockIdx.x * TW + threadIdx.x;
+    if (idx >= P)
+        return;
+    const float t = (float)(*step + 1);
+    const float mi = b1 * m[idx] + (1.0f - b1) * g[idx];
+    const float vi = b2 * v[idx] + (1.0f - b2) * g[idx] * g[idx];
+    m[idx] = mi;
+    v[idx] = vi;
+    const float mh = mi / (1.0f - powf(b1, t));
+    const float vh = vi / (1.0f - powf(b2, t));
+    p[idx] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_steps_inc(int32_t *step, int32_t *local_step)
+{
+    *step += 1;
+    *local_step += 1;
+}
+
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
+// rows order[local_step*B + r] of X/T -> minibatch buffers
+__global__ __launch_bounds__(TW) void k_gather(const float *__restrict__ X,
+                                               const float *__restrict__ T,
+                                               const int32_t *__restrict__ order,
+                                               const int32_t *local_step, int B,
+                                               float *__restrict__ Xb, float *__restrict__ Tb)
+{
+    const int idx = blockIdx.x * TW + threadIdx.x;
+    if (idx >= B * (N_IN + N_OUT))
+        return;
+    const int r = idx / (N_IN + N_OUT), c = idx - r * (N_IN + N_OUT);
+    const int64_t src = order[(int64_t)(*local_step) * B + r];
+    if (c < N_IN)
+        Xb[(int64_t)r * N_IN + c] = X[src * N_IN + c];
+    else
+        Tb[(int64_t)r * N_OUT + (c - N_IN)] = T[src * N_OUT + (c - N_IN)];
+}
+
+// (theta, n_b) from the network output: theta = round(10 clip(o0, .5, .9))/10
+// (the paper's theta grid, Sec. 6.4.1), n_b = 2^clip(round(o1), 5, 12);
+// ok = 0 for non-finite outputs.
+__global__ void k_decode(const float *__restrict__ out, double *theta, int32_t *nb, int32_t *ok)
+{
+    const float o0 = out[0], o1 = out[1];
+    const bool fin = isfinite(o0) && isfinite(o1);
+    *ok = fin ? 1 : 0;
+    const double c = fin ? fmin(fmax((double)o0, 0.5), 0.9) : 0.6;
+    *theta = rint(c * 10.0) / 10.0;
+    const float l = fin ? fminf(fmaxf(rintf(o1), 5.0f), 12.0f) : 8.0f;
+    *nb = 1 << (int)l;
+}
+
+}  // namespace
+}  // namespace mhdc
+
+using namespace mhdc;
+
+struct mhdc_mlp_s {
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    int32_t *step = nullptr, *local_step = nullptr;
+    int32_t cap = 0;  // minibatch capacity of the buffers below
+    float *Xb = nullptr, *Tb = nullptr, *h1 = nullptr, *h2 = nullptr, *out = nullptr;
+    float *d_out = nullptr, *d_h2 = nullptr, *d_h1 = nullptr, *loss = nullptr;
+};
+
+namespace {
+
+void free_buffers(mhdc_mlp_s *M)
+{
+    for (float *q : {M->Xb, M->Tb, M->h1, M->h2, M->out, M->d_out, M->d_h2, M->d_h1})
+        dfree(q);
+    M->Xb = M->Tb = M->h1 = M->h2 = M->out = M->d_out = M->d_h2 = M->d_h1 = nullptr;
+    M->cap = 0;
+}
+
+int ensure_buffers(mhdc_mlp_s *M, int32_t B)
+{
+    if (B <= M->cap)
+        return MHDC_OK;
+    free_buffers(M);
+    int rc;
+    const size_t f = sizeof(float);
+    if ((rc = dmalloc((void **)&M->Xb, f * B * N_IN, "mlp Xb")) ||
+        (rc = dmalloc((void **)&M->Tb, f * B * N_OUT, "mlp Tb")) ||
+        (rc = dmalloc((void **)&M->h1, f * B * HID, "mlp h1")) ||
+        (rc = dmalloc((void **)&M->h2, f * B * HID, "mlp h2")) ||
+        (rc = dmalloc((void **)&M->out, f * B * N_OUT, "mlp out")) ||
+        (rc = dmalloc((void **)&M->d_out, f * B * N_OUT, "mlp d_out")) ||
+        (rc = dmalloc((void **)&M->d_h2, f * B * HID, "mlp d_h2")) ||
+        (rc = dmalloc((void **)&M->d_h1, f * B * HID, "mlp d_h1"))) {
+        free_buffers(M);
+        return rc;
+    }
+    M->cap = B;
+    return MHDC_OK;
+}
+
+void enqueue_forward(mhdc_mlp_s *M, const float *X, int B, hipStream_t s)
+{
+    k_dense_fwd<<<blocks_for(B * HID), TW, 0, s>>>(X, N_IN, M->p + P_W1, M->p + P_B1, HID, M->h1, B, 1);
+    k_dense_fwd<<<blocks_for(B * HID), TW, 0, s>>>(M->h1, HID, M->p + P_W2, M->p + P_B2, HID, M->h2, B, 1);
+    k_dense_fwd<<<blocks_for(B * N_OUT), TW, 0, s>>>(M->h2, HID, M->p + P_W3, M->p + P_B3, N_OUT, M->out, B, 0);
+}
+
+void enqueue_backward(mhdc_mlp_s *M, const float *X, int B, hipStream_t s)
+{
+    k_dense_bwd_w<<<blocks_for(N_OUT * (HID + 1)), TW, 0, s>>>(M->d_out, M->h2, B, HID, N_OUT, M->g + P_W3, M->g + P_B3);
+    k_dense_bwd_x<<<blocks_for(B * HID), TW, 0, s>>>(M->d_out, M->p + P_W3, M->h2, B, HID, N_OUT, M->d_h2);
+    k_dense_bwd_w<<<blocks_for(HID * (HID + 1)), TW, 0, s>>>(M->d_h2, M->h1, B, HID, HID, M->g + P_W2, M->g + P_B2);
+    k_dense_bwd_x<<<blocks_for(B * HID), TW, 0, s>>>(M->d_h2, M->p + P_W2, M->h1, B, HID, HID, M->d_h1);
+    k_dense_bwd_w<<<blocks_for(HID * (N_IN + 1)), TW, 0, s>>>(M->d_h1, X, B, N_IN, HID, M->g + P_W1, M->g + P_B1);
+}
+
+int launch_ok(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MHDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhdc_features(int32_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                  float *feat, hipStream_t stream)
+{
+    clear_error();
+    if (n < 1 || !feat)
+        return set_error(MHDC_ERR_INVALID_ARG, "n >= 1 and a feature buffer are required");
+    (void)hipStreamSynchronize(stream);
+    int64_t nnz = 0;
+    int rc = validate_csr(n, rowptr, colind, val, &nnz);
+    if (rc)
+        return rc;
+    const int64_t n_blk = ((int64_t)n + PROBE_NB - 1) / PROBE_NB;
+    unsigned long long *sums = nullptr;
+    int32_t *gkeys = nullptr, *gcnts = nullptr;
+    if ((rc = dmalloc((void **)&sums, sizeof(unsigned long long) * 2 * N_BINS, "feature sums")))
+        return rc;
+    // the census needs the global table only for blocks of >= 8192 entries;
+    // find the largest block from a host copy of the row pointer
+    int64_t maxm = 0;
+    std::vector<int32_t> hrp((size_t)n + 1);
+    hipError_t e = hipMemcpy(hrp.data(), rowptr, sizeof(int32_t) * ((size_t)n + 1),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        dfree(sums);
+        return set_error(MHDC_ERR_HIP, std::string("features: ") + hipGetErrorString(e));
+    }
+    for (int64_t ib = 0; ib < n_blk; ib++) {
+        const int64_t r1 = std::min<int64_t>(n, (ib + 1) * PROBE_NB);
+        maxm = std::max<int64_t>(maxm, hrp[r1] - hrp[ib * PROBE_NB]);
+    }
+    if (maxm >= CENSUS_LDS_SLOTS) {
+        const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
+        if ((rc = dmalloc((void **)&gkeys, sizeof(int32_t) * 2 * nz, "feature table")) ||
+            (rc = dmalloc((void **)&gcnts, sizeof(int32_t) * 2 * nz, "feature table"))) {
+            dfree(sums);
+            dfree(gkeys);
+            return rc;
+        }
+    }
+    (void)hipMemsetAsync(sums, 0, sizeof(unsigned long long) * 2 * N_BINS, stream);
+    const unsigned grid = (unsigned)std::min<int64_t>(n_blk, 2048);
+    k_feat_census<<<grid, CENSUS_WG, 0, stream>>>(n, n_blk, rowptr, colind, val, gkeys, gcnts,
+                                                   sums);
+    k_feat_finish<<<1, 128, 0, stream>>>(n, nnz, n_blk, sums, feat);
+    rc = launch_ok("features");
+    if (hipStreamSynchronize(stream) != hipSuccess && !rc)
+        rc = set_error(MHDC_ERR_HIP, "features: synchronize failed");
+    dfree(sums);
+    dfree(gkeys);
+    dfree(gcnts);
+    return rc;
+}
+
+mhdc_mlp mhdc_mlp_create(const float *params_host)
+{
+    clear_error();
+    if (!params_host) {
+        set_error(MHDC_ERR_INVALID_ARG, "initial parameters are required");
+        return nullptr;
+    }
+    mhdc_mlp_s *M = new (std::nothrow) mhdc_mlp_s;
+    if (!M) {
+        set_error(MHDC_ERR_OOM, "host allocation of the network failed");
+        return nullptr;
+    }
+    const size_t pb = sizeof(float) * N_PARAMS;
+    int rc;
+    if ((rc = dmalloc((void **)&M->p, pb, "mlp params")) ||
+        (rc = dmalloc((void **)&M->g, pb, "mlp grads")) ||
+        (rc = dmalloc((void **)&M->m, pb, "mlp adam m")) ||
+        (rc = dmalloc((void **)&M->v, pb, "mlp adam v")) ||
+        (rc = dmalloc((void **)&M->step, 2 * sizeof(int32_t), "mlp step"))) {
+        mhdc_mlp_destroy(M);
+        return nullptr;
+    }
+    M->local_step = M->step + 1;
+    if (hipMemcpy(M->p, params_host, pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(M->g, 0, pb) != hipSuccess || hipMemset(M->m, 0, pb) != hipSuccess ||
+        hipMemset(M->v, 0, pb) != hipSuccess ||
+        hipMemset(M->step, 0, 2 * sizeof(int32_t)) != hipSuccess) {
+        set_error(MHDC_ERR_HIP, "initialising the network failed");
+        mhdc_mlp_destroy(M);
+        return nullptr;
+    }
+    return M;
+}
+
+int mhdc_mlp_get_params(mhdc_mlp M, float *params_host)
+{
+    clear_error();
+    if (!M || !params_host)
+        return set_error(MHDC_ERR_INVALID_ARG, "network or buffer is NULL");
+    MHDC_HIP_CHECK(hipDeviceSynchronize());
+    MHDC_HIP_CHECK(hipMemcpy(params_host, M->p, sizeof(float) * N_PARAMS, hipMemcpyDeviceToHost));
+    return MHDC_OK;
+}
+
+int mhdc_mlp_forward(mhdc_mlp M, const float *X, int32_t B, float *out, hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !out || B < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "network, X, out and B >= 1 required");
+    MHDC_HIP_CHECK(hipStreamSynchronize(stream));
+    int rc = ensure_buffers(M, B);
+    if (rc)
+        return rc;
+    enqueue_forward(M, X, B, stream);
+    MHDC_HIP_CHECK(hipMemcpyAsync(out, M->out, sizeof(float) * B * N_OUT,
+                                  hipMemcpyDeviceToDevice, stream));
+    return launch_ok("mlp forward");
+}
+
+int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, float w0,
+                       float w1, float *loss, float *grad, hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !T || !loss || !grad || B < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "network, X, T, loss, grad and B >= 1 required");
+    MHDC_HIP_CHECK(hipStreamSynchronize(stream));
+    int rc = ensure_buffers(M, B);
+    if (rc)
+        return rc;
+    enqueue_forward(M, X, B, stream);
+    k_loss_grad<<<1, TW, 0, stream>>>(M->out, T, B, w0, w1, M->d_out, loss, nullptr);
+    enqueue_backward(M, X, B, stream);
+    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice,
+                                  stream));
+    return launch_ok("mlp loss/grad");
+}
+
+int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const int32_t *order,
+                   int64_t steps, int32_t B, float lr, float w0, float w1, float *loss_hist,
+                   hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !T || !order || !loss_hist || N < 1 || B < 1 || steps < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "bad training arguments");
+    if (steps * (int64_t)B > INT32_MAX)
+        return set_error(MHDC_ERR_SIZE, "steps * B exceeds the order index range");
+    MHDC_HIP_CHECK(hipStreamSynchronize(stream));
+    int rc = ensure_buffers(M, B);
+    if (rc)
+        return rc;
+    // capture one step: gather, forward, loss, backward, Adam, counters
+    hipStream_t cs = nullptr;
+    MHDC_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    k_zero_i32<<<1, 1, 0, cs>>>(M->local_step);
+    hipError_t e = hipStreamSynchronize(cs);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        k_gather<<<blocks_for(B * (N_IN + N_OUT)), TW, 0, cs>>>(X, T, order, M->local_step, B, M->Xb, M->Tb);
+        enqueue_forward(M, M->Xb, B, cs);
+        k_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, w0, w1, M->d_out, loss_hist, M->local_step);
+        enqueue_backward(M, M->Xb, B, cs);
+        k_adam<<<blocks_for(N_PARAMS), TW, 0, cs>>>(M->p, M->g, M->m, M->v, N_PARAMS, lr, 0.9f, 0.999f, 1e-8f, M->step);
+        k_steps_inc<<<1, 1, 0, cs>>>(M->step, M->local_step);
+        e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+        for (int64_t t = 0; t < steps && e == hipSuccess; t++)
+            e = hipGraphLaunch(exec, cs);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(cs);
+    if (exec)
+        (void)hipGraphExecDestroy(exec);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string("mlp train: ") + hipGetErrorString(e));
+    return MHDC_OK;
+}
+
+void mhdc_mlp_destroy(mhdc_mlp M)
+{
+    if (!M)
+        return;
+    free_buffers(M);
+    dfree(M->p);
+    dfree(M->g);
+    dfree(M->m);
+    dfree(M->v);
+    dfree(M->step);
+    delete M;
+}
+
+mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
+                        const double *val, mhdc_mlp model, double tolerance,
+                        mhdc_select_result *out)
+{
+    clear_error();
+    const double rule_theta = 0.6;
+    const int32_t rule_nb = 256;
+    mhdc_select_result res{};
+    res.theta = rule_theta;
+    res.n_b = rule_nb;
+    res.used_rule = 1;
+    mhdc_handle net = nullptr;
+    if (model) {
+        float *feat = nullptr, *o = nullptr;
+        double *th = nullptr;
+        int32_t *nbok = nullptr;
+        int rc = dmalloc((void **)&feat, sizeof(float) * N_IN, "select features");
+        if (!rc)
+            rc = dmalloc((void **)&o, sizeof(float) * N_OUT, "select out");
+        if (!rc)
+            rc = dmalloc((void **)&th, sizeof(double), "select theta");
+        if (!rc)
+            rc = dmalloc((void **)&nbok, 2 * sizeof(int32_t), "select nb");
+        if (!rc)
+            rc = mhdc_features(n, rowptr, colind, val, feat, 0);
+        if (!rc)
+            rc = mhdc_mlp_forward(model, feat, 1, o, 0);
+        double h_th = 0.6;
+        int32_t h_nbok[2] = {0, 0};
+        if (!rc) {
+            k_decode<<<1, 1>>>(o, th, nbok, nbok + 1);
+            if (hipMemcpy(&h_th, th, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(h_nbok, nbok, sizeof(h_nbok), hipMemcpyDeviceToHost) != hipSuccess)
+                rc = set_error(MHDC_ERR_HIP, "select: reading the decision failed");
+        }
+        dfree(feat);
+        dfree(o);
+        dfree(th);
+        dfree(nbok);
+        if (rc)
+            return nullptr;
+        res.theta_net = h_th;
+        res.n_b_net = h_nbok[0];
+        res.net_ok = h_nbok[1];
+        if (res.net_ok) {
+            net = mhdc_from_csr(n, rowptr, colind, val, res.n_b_net, res.theta_net);
+            if (!net)
+                return nullptr;
+        }
+    }
+    mhdc_handle rule = mhdc_from_csr(n, rowptr, colind, val, rule_nb, rule_theta);
+    if (!rule) {
+        if (net)
+            mhdc_destroy(net);
+        return nullptr;
+    }
+    mhdc_info ir{}, in{};
+    (void)mhdc_get_info(rule, &ir);
+    res.bytes_rule = ir.bytes_paper;
+    mhdc_handle pick = rule;
+    if (net) {
+        (void)mhdc_get_info(net, &in);
+        res.bytes_net = in.bytes_paper;
+        // the paper's byte model judges: keep the network's choice unless
+        // it is predicted to move more than (1 + tolerance) x the policy's
+        if (in.bytes_paper <= (1.0 + tolerance) * ir.bytes_paper) {
+            pick = net;
+            res.theta = res.theta_net;
+            res.n_b = res.n_b_net;
+            res.used_rule = 0;
+        }
+    }
+    if (pick != rule)
+        mhdc_destroy(rule);
+    if (net && pick != net)
+        mhdc_destroy(net);
+    if (out)
+        *out = res;
+    return pick;
+}
+
+}  // extern "C"

@@ -59,6 +59,20 @@ class TuneResult(ctypes.Structure):
                 ("tried", ctypes.c_int32)]
 
 
+class SelectResult(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("n_b", ctypes.c_int32),
+                ("used_rule", ctypes.c_int32), ("theta_net", ctypes.c_double),
+                ("n_b_net", ctypes.c_int32), ("net_ok", ctypes.c_int32),
+                ("bytes_net", ctypes.c_double), ("bytes_rule", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+MLP_PARAMS = 25346
+MLP_IN = 66
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -105,6 +119,16 @@ SIGNATURES = {
                             ctypes.POINTER(TuneResult)]),
     "mhdc_batch_tune": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_i32),
                                        ctypes.POINTER(ctypes.c_float)]),
+    "mhdc_features": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp]),
+    "mhdc_mlp_create": (_vp, [_vp]),
+    "mhdc_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
+    "mhdc_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
+    "mhdc_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float,
+                                          _vp, _vp, _vp]),
+    "mhdc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i64, _i32, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, _vp, _vp]),
+    "mhdc_mlp_destroy": (None, [_vp]),
+    "mhdc_select": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, ctypes.POINTER(SelectResult)]),
 }
 
 
@@ -391,6 +415,82 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def features(rowptr, colind, val, stream=None):
+    """66 selector features of a device CSR matrix (float32 device tensor)."""
+    n, rp, ci, v = _csr_args(rowptr, colind, val)
+    f = torch.empty(MLP_IN, dtype=torch.float32, device=rowptr.device)
+    _check(lib().mhdc_features(n, rp, ci, v, ctypes.c_void_p(f.data_ptr()), _stream(stream)))
+    return f
+
+
+class MLP:
+    """The 66 -> 128 -> 128 -> 2 selector network on the device."""
+
+    def __init__(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != MLP_PARAMS:
+            raise ValueError("expected %d parameters" % MLP_PARAMS)
+        self._h = lib().mhdc_mlp_create(p.ctypes.data_as(ctypes.c_void_p))
+        if not self._h:
+            _raise()
+
+    def params(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, np.float32)
+        _check(lib().mhdc_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def forward(self, X, stream=None):
+        B = X.shape[0]
+        out = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+        _check(lib().mhdc_mlp_forward(self._h, _dptr(X, torch.float32, "X"), B,
+                                      _dptr(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def loss_grad(self, X, T, w=(1.0, 1.0), stream=None):
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        _check(lib().mhdc_mlp_loss_grad(self._h, _dptr(X, torch.float32, "X"),
+                                        _dptr(T, torch.float32, "T"), X.shape[0], float(w[0]),
+                                        float(w[1]), _dptr(loss, torch.float32, "loss"),
+                                        _dptr(grad, torch.float32, "grad"), _stream(stream)))
+        return loss, grad
+
+    def train(self, X, T, order, steps, B, lr, w=(1.0, 1.0), stream=None):
+        """Adam over minibatches order[s*B:(s+1)*B] (int32 device tensor)."""
+        hist = torch.empty(int(steps), dtype=torch.float32, device=X.device)
+        _check(lib().mhdc_mlp_train(self._h, _dptr(X, torch.float32, "X"),
+                                    _dptr(T, torch.float32, "T"), X.shape[0],
+                                    _dptr(order, torch.int32, "order"), int(steps), int(B),
+                                    float(lr), float(w[0]), float(w[1]),
+                                    _dptr(hist, torch.float32, "loss_hist"), _stream(stream)))
+        return hist
+
+    def close(self):
+        if self._h:
+            lib().mhdc_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def select(rowptr, colind, val, model=None, tolerance=0.05):
+    """Choose (theta, n_b) with the network (None: the policy 0.6 / 256),
+    judged by the byte model; returns (MHDCMatrix, result dict)."""
+    n, rp, ci, v = _csr_args(rowptr, colind, val)
+    res = SelectResult()
+    h = lib().mhdc_select(n, rp, ci, v, model._h if model is not None else None,
+                          float(tolerance), ctypes.byref(res))
+    if not h:
+        _raise()
+    return MHDCMatrix(h, n), res.as_dict()
 
 
 def stream_direct(A, B, C, stream=None):

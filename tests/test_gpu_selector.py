@@ -1,0 +1,143 @@
+"""GPU side of the learned selector through the C-ABI: the census features
+against the oracle bit for bit, the network's forward pass and gradient
+against the FP64 oracle, Adam training against the oracle's Adam, training
+determinism, and mhdc_select's judge and fallback."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import selector as S
+from paper_2105_04937_amd import mhdc, synth
+from tests.gpu_helpers import assert_oracle_bits, dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _feature_cases():
+    return [
+        synth.random_csr(300, 1, density=0.02, bands=[0, 1, -7, 40], zero_frac=0.1),
+        synth.random_csr(600, 2, density=0.1, bands=[0, 3]),  # > 8192 entries per block
+        synth.laplacian7(16),
+        synth.partially_diagonal(20, 4),
+        synth.heptadiagonal(24, 5),
+        synth.random_csr(1, 3, density=1.0),
+    ]
+
+
+@pytest.mark.parametrize("m", _feature_cases(), ids=lambda m: "n%d" % m.n)
+def test_features_match_oracle(m):
+    say("case: features n=%d nnz=%d" % (m.n, m.nnz))
+    f = mhdc.features(*dev(m)).cpu().numpy()
+    want = S.features(m.rowptr, m.colind, m.val)
+    assert np.array_equal(f[:64].view(np.int32), want[:64].view(np.int32))
+    # log2 terms: one float32 ulp at most
+    assert np.all(np.abs(f[64:].view(np.int32) - want[64:].view(np.int32)) <= 1)
+
+
+def _params(seed, noise=0.05):
+    rng = np.random.default_rng(seed)
+    p = S.init_params(seed)
+    return (p + rng.normal(0, noise, p.size)).astype(np.float32)
+
+
+def test_forward_and_gradient_match_oracle():
+    say("case: mlp forward / gradient")
+    rng = np.random.default_rng(0)
+    p = _params(1)
+    net = mhdc.MLP(p)
+    for B in (1, 37, 128):
+        X = rng.uniform(0, 1, size=(B, 66)).astype(np.float32)
+        T = rng.normal(size=(B, 2)).astype(np.float32)
+        Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+        out = net.forward(Xd).cpu().numpy()
+        ref, _ = S.forward(p, X)
+        assert np.allclose(out, ref, rtol=1e-5, atol=1e-5)
+        loss, g = net.loss_grad(Xd, Td, w=(25.0, 0.1))
+        L, gref = S.loss_and_grad(p, X, T, w=(25.0, 0.1))
+        assert abs(loss.item() - L) <= 1e-5 * max(1.0, abs(L))
+        g = g.cpu().numpy()
+        assert np.allclose(g, gref, rtol=1e-3, atol=1e-5 * np.abs(gref).max())
+    net.close()
+
+
+def test_training_matches_oracle_adam_and_is_deterministic():
+    say("case: mlp training")
+    rng = np.random.default_rng(5)
+    N, B, steps, lr = 300, 32, 6, 1e-3
+    X = rng.uniform(0, 1, size=(N, 66)).astype(np.float32)
+    T = np.stack([0.5 + 0.4 * X[:, 3], 5 + 7 * X[:, 10]], axis=1).astype(np.float32)
+    order = np.concatenate([rng.permutation(N)[:B] for _ in range(steps)]).astype(np.int32)
+    p0 = _params(7, noise=0.0)
+    Xd, Td, od = (torch.from_numpy(a).cuda() for a in (X, T, order))
+    net = mhdc.MLP(p0)
+    hist = net.train(Xd, Td, od, steps, B, lr, w=(25.0, 0.1)).cpu().numpy()
+    p_gpu = net.params()
+    # oracle: the same minibatches, FP64 backprop and Adam
+    p = p0.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(steps):
+        idx = order[t * B:(t + 1) * B]
+        L, g = S.loss_and_grad(p, X[idx], T[idx], w=(25.0, 0.1))
+        assert abs(hist[t] - L) <= 1e-4 * max(1.0, L)
+        p, m, v = S.adam(p, g, m, v, t + 1, lr)
+    d = np.abs(p_gpu - p)
+    assert d.max() <= 2 * steps * lr          # an Adam step moves a weight by at most ~lr
+    assert np.quantile(d, 0.99) <= 1e-5       # and nearly all agree to FP32 accuracy
+    # determinism: the same start and order give the same bits
+    net2 = mhdc.MLP(p0)
+    net2.train(Xd, Td, od, steps, B, lr, w=(25.0, 0.1))
+    assert np.array_equal(net2.params().view(np.int32), p_gpu.view(np.int32))
+
+
+def test_training_reduces_loss():
+    say("case: mlp training reduces loss")
+    rng = np.random.default_rng(9)
+    N, B, steps = 1024, 128, 400
+    X = rng.uniform(0, 1, size=(N, 66)).astype(np.float32)
+    T = np.stack([0.5 + 0.4 * X[:, 0] * X[:, 1], 5 + 7 * X[:, 40]], axis=1).astype(np.float32)
+    order = np.concatenate([rng.permutation(N)[:B] for _ in range(steps)]).astype(np.int32)
+    net = mhdc.MLP(S.init_params(3))
+    hist = net.train(*(torch.from_numpy(a).cuda() for a in (X, T, order)), steps, B, 3e-3,
+                     w=(25.0, 0.1)).cpu().numpy()
+    assert hist[-20:].mean() < 0.1 * hist[:5].mean()
+
+
+def _fixed_net(theta, log2nb):
+    p = np.zeros(S.N_PARAMS, np.float32)
+    p[-2], p[-1] = theta, log2nb   # b3: constant output
+    return mhdc.MLP(p)
+
+
+def test_select_policy_network_and_judge():
+    m = synth.partially_diagonal(24, 12)
+    say("case: select n=%d" % m.n)
+    d = dev(m)
+    x = synth.vector(m.n, 1)
+    xd = torch.from_numpy(x).cuda()
+    h, r = mhdc.select(*d, model=None)
+    assert (r["theta"], r["n_b"], r["used_rule"]) == (0.6, 256, 1)
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6)
+    assert_oracle_bits(h.spmv(xd), oracle.mhdc_spmv(ref, x), "policy")
+    # a network that always proposes (0.7, 128): kept when the model allows it
+    net = _fixed_net(0.68, 7.2)
+    h, r = mhdc.select(*d, model=net, tolerance=1e9)
+    assert (r["theta_net"], r["n_b_net"], r["net_ok"]) == (0.7, 128, 1)
+    assert (r["theta"], r["n_b"], r["used_rule"]) == (0.7, 128, 0)
+    inf = h.info()
+    assert (inf["n_b"], inf["theta"]) == (128, 0.7)
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 128, 0.7)
+    assert_oracle_bits(h.spmv(xd), oracle.mhdc_spmv(ref, x), "network choice")
+    # the judge: a proposal the byte model rates worse than the policy is refused
+    bad = _fixed_net(0.9, 12.0)
+    h, r = mhdc.select(*d, model=bad, tolerance=0.0)
+    if r["bytes_net"] > r["bytes_rule"]:
+        assert r["used_rule"] == 1 and (r["theta"], r["n_b"]) == (0.6, 256)
+    else:
+        assert r["used_rule"] == 0
+    # non-finite output: fallback
+    p = np.zeros(S.N_PARAMS, np.float32)
+    p[-2] = np.nan
+    h, r = mhdc.select(*d, model=mhdc.MLP(p))
+    assert r["net_ok"] == 0 and r["used_rule"] == 1

@@ -94,5 +94,5 @@ def test_adam_first_step_closed_form():
 
 
 def test_decode():
-    th, nb = S.decode([[0.3, 4.2], [0.72, 7.6], [1.5, 20.0]])
-    assert list(th) == [0.5, 0.72, 0.9] and list(nb) == [32, 256, 4096]
+    th, nb = S.decode([[0.3, 4.2], [0.72, 7.6], [1.5, 20.0], [0.649, 8.5]])
+    assert list(th) == [0.5, 0.7, 0.9, 0.6] and list(nb) == [32, 256, 4096, 256]
