@@ -246,6 +246,12 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr,
                           double threshold, int32_t nrhs,
                           const int32_t *nb_candidates, int32_t n_candidates,
                           hipStream_t stream, mhdc_tune_result *out);
+/* Mean time of one mhdc_spmv(h, x, y) in microseconds: HIP events around
+ * back-to-back launches issued from C on `stream` (the count grows until
+ * the window is >= 0.2 ms; best of 4 windows, after 2 warm-up calls), so
+ * host-side call overhead does not enter.  Overwrites y.  Synchronous. */
+int mhdc_time_spmv(mhdc_handle h, const double *x, double *y, hipStream_t stream,
+                   float *us);
 /* Time the batch under wg_size 64 and 256, keep the faster.  Runs the
  * batch, so the bound Y blocks are overwritten.  Synchronous. */
 int mhdc_batch_tune(mhdc_batch b, hipStream_t stream, int32_t *best_wg,
@@ -293,6 +299,12 @@ int mhdc_mlp_loss_grad(mhdc_mlp m, const float *X, const float *T, int32_t B,
 int mhdc_mlp_train(mhdc_mlp m, const float *X, const float *T, int32_t N,
                    const int32_t *order, int64_t steps, int32_t B, float lr,
                    float w0, float w1, float *loss_hist, hipStream_t stream);
+/* Decisions for B feature rows: theta[r] = round(10 clip(o_r0, 0.5, 0.9))/10
+ * (the theta grid of Sec. 6.4.1), n_b[r] = 2^clip(round(o_r1), 5, 12),
+ * ok[r] = 0 (and the policy 0.6 / 256) for a non-finite output.  Device
+ * arrays; asynchronous on stream. */
+int mhdc_mlp_decide(mhdc_mlp m, const float *X, int32_t B, double *theta,
+                    int32_t *n_b, int32_t *ok, hipStream_t stream);
 void mhdc_mlp_destroy(mhdc_mlp m);
 
 typedef struct {

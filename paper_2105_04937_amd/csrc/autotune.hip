@@ -132,6 +132,15 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr, const int32_t *colin
     return best;
 }
 
+int mhdc_time_spmv(mhdc_handle h, const double *x, double *y, hipStream_t stream, float *us)
+{
+    clear_error();
+    if (!h || !us)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle and us are required");
+    return time_us([&] { return launch_spmv(h->m, x, h->m.n, y, h->m.n, 1, stream); }, stream,
+                   us);
+}
+
 int mhdc_batch_tune(mhdc_batch b, hipStream_t stream, int32_t *best_wg, float *best_us)
 {
     clear_error();

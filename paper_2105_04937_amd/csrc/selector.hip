@@ -237,18 +237,22 @@ __global__ __launch_bounds__(TW) void k_gather(const float *__restrict__ X,
         Tb[(int64_t)r * N_OUT + (c - N_IN)] = T[src * N_OUT + (c - N_IN)];
 }
 
-// (theta, n_b) from the network output: theta = round(10 clip(o0, .5, .9))/10
-// (the paper's theta grid, Sec. 6.4.1), n_b = 2^clip(round(o1), 5, 12);
-// ok = 0 for non-finite outputs.
-__global__ void k_decode(const float *__restrict__ out, double *theta, int32_t *nb, int32_t *ok)
+// (theta, n_b) from each network output row: theta = round(10 clip(o0, .5,
+// .9))/10 (the paper's theta grid, Sec. 6.4.1), n_b = 2^clip(round(o1), 5,
+// 12); ok = 0 for non-finite outputs (then theta = 0.6, n_b = 256).
+__global__ void k_decode(const float *__restrict__ out, int B, double *theta, int32_t *nb,
+                         int32_t *ok)
 {
-    const float o0 = out[0], o1 = out[1];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B)
+        return;
+    const float o0 = out[2 * r], o1 = out[2 * r + 1];
     const bool fin = isfinite(o0) && isfinite(o1);
-    *ok = fin ? 1 : 0;
+    ok[r] = fin ? 1 : 0;
     const double c = fin ? fmin(fmax((double)o0, 0.5), 0.9) : 0.6;
-    *theta = rint(c * 10.0) / 10.0;
+    theta[r] = rint(c * 10.0) / 10.0;
     const float l = fin ? fminf(fmaxf(rintf(o1), 5.0f), 12.0f) : 8.0f;
-    *nb = 1 << (int)l;
+    nb[r] = 1 << (int)l;
 }
 
 }  // namespace
@@ -503,6 +507,21 @@ int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const 
     return MHDC_OK;
 }
 
+int mhdc_mlp_decide(mhdc_mlp M, const float *X, int32_t B, double *theta, int32_t *n_b,
+                    int32_t *ok, hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !theta || !n_b || !ok || B < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "network, X, outputs and B >= 1 required");
+    MHDC_HIP_CHECK(hipStreamSynchronize(stream));
+    int rc = ensure_buffers(M, B);
+    if (rc)
+        return rc;
+    enqueue_forward(M, X, B, stream);
+    k_decode<<<blocks_for(B), TW, 0, stream>>>(M->out, B, theta, n_b, ok);
+    return launch_ok("mlp decide");
+}
+
 void mhdc_mlp_destroy(mhdc_mlp M)
 {
     if (!M)
@@ -546,7 +565,7 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
         double h_th = 0.6;
         int32_t h_nbok[2] = {0, 0};
         if (!rc) {
-            k_decode<<<1, 1>>>(o, th, nbok, nbok + 1);
+            k_decode<<<1, 1>>>(o, 1, th, nbok, nbok + 1);
             if (hipMemcpy(&h_th, th, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(h_nbok, nbok, sizeof(h_nbok), hipMemcpyDeviceToHost) != hipSuccess)
                 rc = set_error(MHDC_ERR_HIP, "select: reading the decision failed");

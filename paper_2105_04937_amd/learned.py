@@ -1,0 +1,269 @@
+"""Learned (theta, n_b) selector: data collection, training, evaluation.
+
+The paper proposes a policy for M-HDC's two parameters (50 <~ bl <~ 500,
+theta = 0.6; Sec. 6.4.3) and leaves their choice open (Sec. 7).  Here:
+
+* collect: draw matrices of the stencil families (7/19/27-point grids with
+  per-octant or global coupling drops and random extra columns, grid side
+  U{48..144}), compute the 66 census features (mhdc_features), and time the
+  M-HDC SpMV for every (theta, n_b) of the grid theta in {0.5 .. 0.9}
+  (Sec. 6.4.1's values) x n_b in {32 .. 4096} (mhdc_from_csr +
+  mhdc_time_spmv).  One JSON line per matrix.
+* train: the target of a matrix is its measured arg-min over the grid with
+  near-ties broken towards the best fixed grid point of the training set
+  (see target()); the network is trained with the library's own kernels
+  (mhdc_mlp_train: forward, backward, Adam).
+* evaluate: the network's decisions (mhdc_mlp_decide) are looked up in the
+  measured grid of held-out matrices, after the byte-model judge that
+  mhdc_select applies, and compared with the exhaustive best and the policy.
+
+Everything that computes on matrices or the network runs in the library's
+kernels; this module draws random inputs, keeps records and forms targets.
+
+    python -m paper_2105_04937_amd.learned collect --split train --start 0 --count 1000 --out F
+    python -m paper_2105_04937_amd.learned train --data A B ... --test T --out-dir D
+"""
+from __future__ import annotations
+
+import argparse
+import gzip
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+THETAS = (0.5, 0.6, 0.7, 0.8, 0.9)
+NBS = (32, 64, 128, 256, 512, 1024, 2048, 4096)
+RULE = (0.6, 256)
+SEED_BASE = {"train": 5000, "test": 9000}
+LOSS_W = (25.0, 0.25)       # 1/0.2^2 for theta, 1/2^2 for log2 n_b
+HERE = os.path.dirname(os.path.abspath(__file__))
+DATA_DIR = os.path.join(HERE, "selector_data")
+
+
+JUDGE_TOLERANCE = 0.25      # mhdc_select keeps a proposal up to 1.25 x the policy's V
+WEIGHTS = os.path.join(DATA_DIR, "weights.npy")
+
+
+def key(theta, nb):
+    return "%.1f/%d" % (theta, nb)
+
+
+def load_network(path=WEIGHTS):
+    """The trained selector network (parameters stored as float32 .npy)."""
+    from paper_2105_04937_amd import mhdc
+    return mhdc.MLP(np.load(path, allow_pickle=False))
+
+
+def draw_family(rng):
+    """Matrix parameters of one sample (drawn from its own seed)."""
+    N = int(rng.integers(48, 145))
+    if rng.random() < 0.15:
+        return dict(N=N, points=7, drop=0.0, extra=0, family="hepta")
+    points = int(rng.choice([7, 19, 27]))
+    if rng.random() < 0.5:
+        drop = [float(a) for a in rng.uniform(0.0, 0.95, size=8)]
+        fam = "octant"
+    else:
+        drop = float(rng.uniform(0.0, 0.6))
+        fam = "global"
+    extra = int(rng.choice([0, 0, 1, 2, 4]))
+    return dict(N=N, points=points, drop=drop, extra=extra, family=fam)
+
+
+def collect(split, start, count, out_path):
+    import torch
+
+    from paper_2105_04937_amd import mhdc, synth
+    mhdc.lib()
+    with open(out_path, "a") as out:
+        for i in range(start, start + count):
+            t0 = time.time()
+            seed = SEED_BASE[split] + i
+            fam = draw_family(np.random.default_rng(seed))
+            rp, ci, v = synth.stencil_matrix_gpu(fam["N"], seed, points=fam["points"],
+                                                 drop=fam["drop"], extra_per_row=fam["extra"])
+            n, nnz = rp.numel() - 1, ci.numel()
+            feat = mhdc.features(rp, ci, v).cpu().numpy()
+            g = torch.Generator(device="cuda")
+            g.manual_seed(seed)
+            x = torch.rand(n, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+            y = torch.empty_like(x)
+            us, vb = {}, {}
+            for th in THETAS:
+                for nb in NBS:
+                    h = mhdc.MHDCMatrix.from_csr(rp, ci, v, nb, th)
+                    vb[key(th, nb)] = h.info()["bytes_paper"]
+                    us[key(th, nb)] = round(h.time_spmv(x, y), 3)
+                    h.close()
+            rec = dict(id=i, split=split, seed=seed, family=fam, n=n, nnz=nnz,
+                       features=[float(f) for f in feat], us=us, bytes_paper=vb)
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+            best = min(us, key=us.get)
+            print("%s %d n=%d nnz=%d best=%s %.1fus rule=%.1fus (%.1fs)" % (
+                split, i, n, nnz, best, us[best], us[key(*RULE)], time.time() - t0), flush=True)
+            del rp, ci, v, x, y
+
+
+def load(paths):
+    recs = []
+    for p in paths:
+        op = gzip.open if p.endswith(".gz") else open
+        with op(p, "rt") as f:
+            recs.extend(json.loads(l) for l in f if l.strip())
+    return recs
+
+
+def grid_coords(ks):
+    th = np.array([float(k.split("/")[0]) for k in ks])
+    lb = np.array([math.log2(int(k.split("/")[1])) for k in ks])
+    return th, lb
+
+
+def prior_point(recs):
+    """The grid point with the lowest mean time ratio t / t_best over the
+    training matrices (the best single fixed choice)."""
+    ks = list(recs[0]["us"])
+    R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in recs])
+    return ks[int(np.argmin(R.mean(axis=0)))]
+
+
+def target(rec, prior, eps=0.02):
+    """Training target: the grid point minimising t/t_min + eps * (grid steps
+    from the prior point), i.e. the measured arg-min with near-ties (the
+    landscape is flat within timing noise and has several distant minima)
+    broken towards the best fixed choice.  Averaging near-best points
+    instead (a soft arg-min) regresses between distant minima."""
+    ks = list(rec["us"])
+    t = np.array([rec["us"][k] for k in ks])
+    th, lb = grid_coords(ks)
+    pth, plb = grid_coords([prior])
+    score = t / t.min() + eps * (np.abs(lb - plb[0]) + np.abs(th - pth[0]) / 0.1)
+    i = int(np.argmin(score))
+    return np.array([th[i], lb[i]], np.float32)
+
+
+def init_params(seed):
+    """He-uniform weights, zero biases (the order of the C-ABI parameter
+    vector: W1 128x66, b1, W2 128x128, b2, W3 2x128, b3)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in ((128, 66), (128,), (128, 128), (128,), (2, 128), (2,)):
+        if len(shape) == 2:
+            lim = math.sqrt(6.0 / shape[1])
+            parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(recs, steps=8000, B=128, lr=1e-3, seed=0):
+    """Adam on the library's kernels: lr for the first 3/4 of the steps,
+    lr/3 for the rest (the optimizer state carries over)."""
+    import torch
+
+    from paper_2105_04937_amd import mhdc
+    prior = prior_point(recs)
+    X = np.array([r["features"] for r in recs], np.float32)
+    T = np.stack([target(r, prior) for r in recs]).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    per = []
+    while sum(len(p) for p in per) < steps * B:
+        per.append(rng.permutation(len(recs)))
+    order = np.concatenate(per)[:steps * B].astype(np.int32)
+    net = mhdc.MLP(init_params(seed))
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    s1 = (3 * steps) // 4
+    h1 = net.train(Xd, Td, torch.from_numpy(order[:s1 * B]).cuda(), s1, B, lr, w=LOSS_W)
+    h2 = net.train(Xd, Td, torch.from_numpy(order[s1 * B:]).cuda(), steps - s1, B, lr / 3,
+                   w=LOSS_W)
+    return net, np.concatenate([h1.cpu().numpy(), h2.cpu().numpy()]), prior
+
+
+def evaluate(net, recs, tolerance=0.05):
+    """Per held-out matrix: time of the judged network choice, of the policy
+    and of the exhaustive best, all from the measured grid."""
+    import torch
+    X = torch.from_numpy(np.array([r["features"] for r in recs], np.float32)).cuda()
+    th, nb, ok = (t.cpu().numpy() for t in net.decide(X))
+    rows = []
+    for r, t_, b_, o_ in zip(recs, th, nb, ok):
+        us = r["us"]
+        kb = min(us, key=us.get)
+        kr = key(*RULE)
+        kn = key(float(t_), int(b_))
+        use_net = bool(o_) and r["bytes_paper"][kn] <= (1.0 + tolerance) * r["bytes_paper"][kr]
+        ks = kn if use_net else kr
+        rows.append(dict(id=r["id"], best=kb, net=kn, used_net=use_net,
+                         t_best=us[kb], t_sel=us[ks], t_rule=us[kr], t_net=us[kn]))
+    t_best = np.array([x["t_best"] for x in rows])
+    t_sel = np.array([x["t_sel"] for x in rows])
+    t_rule = np.array([x["t_rule"] for x in rows])
+    t_net = np.array([x["t_net"] for x in rows])
+    rep = dict(
+        matrices=len(rows),
+        within_5pct_selected=float(np.mean(t_sel <= 1.05 * t_best)),
+        within_5pct_rule=float(np.mean(t_rule <= 1.05 * t_best)),
+        mean_ratio_selected=float(np.mean(t_sel / t_best)),
+        mean_ratio_rule=float(np.mean(t_rule / t_best)),
+        mean_ratio_network_unjudged=float(np.mean(t_net / t_best)),
+        geomean_speedup_over_rule=float(np.exp(np.mean(np.log(t_rule / t_sel)))),
+        total_time_selected_us=float(t_sel.sum()), total_time_rule_us=float(t_rule.sum()),
+        total_time_best_us=float(t_best.sum()),
+        used_network=float(np.mean([x["used_net"] for x in rows])),
+    )
+    return rep, rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--split", choices=("train", "test"), required=True)
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--count", type=int, default=100)
+    c.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", nargs="+", required=True)
+    t.add_argument("--test", nargs="+", required=True)
+    t.add_argument("--steps", type=int, default=8000)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--out-dir", required=True)
+    a = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    if a.cmd == "collect":
+        collect(a.split, a.start, a.count, a.out)
+        return
+    recs = load(a.data)
+    test = load(a.test)
+    t0 = time.time()
+    net, hist, prior = train(recs, steps=a.steps, lr=a.lr)
+    dt = time.time() - t0
+    os.makedirs(a.out_dir, exist_ok=True)
+    np.save(os.path.join(a.out_dir, "weights.npy"), net.params())
+    rep, rows = evaluate(net, test)
+    rep_train, _ = evaluate(net, recs)
+    judge = {}
+    for tol in (0.0, 0.05, 0.10, 0.25, 1e9):
+        r_, _ = evaluate(net, test, tolerance=tol)
+        judge["%g" % tol] = {k: r_[k] for k in ("within_5pct_selected", "mean_ratio_selected",
+                                                "used_network")}
+    ks = list(test[0]["us"])
+    R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in test])
+    rep.update(train_matrices=len(recs), train_steps=a.steps, train_seconds=round(dt, 2),
+               loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean()),
+               prior=prior, prior_fixed_on_test=dict(
+                   mean_ratio=float(R[:, ks.index(prior)].mean()),
+                   within_5pct=float(np.mean(R[:, ks.index(prior)] <= 1.05))),
+               judge_tolerance_sweep=judge, train_set=rep_train)
+    with open(os.path.join(a.out_dir, "eval_report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    print(json.dumps(rep))
+
+
+if __name__ == "__main__":
+    main()

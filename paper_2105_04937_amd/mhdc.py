@@ -127,7 +127,9 @@ SIGNATURES = {
                                           _vp, _vp, _vp]),
     "mhdc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i64, _i32, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, _vp, _vp]),
+    "mhdc_mlp_decide": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "mhdc_mlp_destroy": (None, [_vp]),
+    "mhdc_time_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
     "mhdc_select": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, ctypes.POINTER(SelectResult)]),
 }
 
@@ -205,6 +207,15 @@ class _Matrix:
         _check(self._fn("spmv")(self._h, _dptr(x, torch.float64, "x"),
                                 _dptr(y, torch.float64, "y"), _stream(stream)))
         return y
+
+    def time_spmv(self, x, y, stream=None):
+        """Mean microseconds per spmv, timed from C with HIP events (M-HDC)."""
+        if self.kind != KIND_MHDC:
+            raise TypeError("time_spmv takes an M-HDC handle")
+        us = ctypes.c_float(0)
+        _check(lib().mhdc_time_spmv(self._h, _dptr(x, torch.float64, "x"),
+                                    _dptr(y, torch.float64, "y"), _stream(stream), ctypes.byref(us)))
+        return us.value
 
     def spmm(self, X, Y=None, stream=None):
         """Y = A X for k right-hand sides given as rows of X, shape (k, n)
@@ -469,6 +480,17 @@ class MLP:
                                     _dptr(hist, torch.float32, "loss_hist"), _stream(stream)))
         return hist
 
+    def decide(self, X, stream=None):
+        """(theta, n_b, ok) device tensors for B feature rows."""
+        B = X.shape[0]
+        th = torch.empty(B, dtype=torch.float64, device=X.device)
+        nb = torch.empty(B, dtype=torch.int32, device=X.device)
+        ok = torch.empty(B, dtype=torch.int32, device=X.device)
+        _check(lib().mhdc_mlp_decide(self._h, _dptr(X, torch.float32, "X"), B,
+                                     _dptr(th, torch.float64, "theta"), _dptr(nb, torch.int32, "n_b"),
+                                     _dptr(ok, torch.int32, "ok"), _stream(stream)))
+        return th, nb, ok
+
     def close(self):
         if self._h:
             lib().mhdc_mlp_destroy(self._h)
@@ -481,7 +503,7 @@ class MLP:
             pass
 
 
-def select(rowptr, colind, val, model=None, tolerance=0.05):
+def select(rowptr, colind, val, model=None, tolerance=0.25):
     """Choose (theta, n_b) with the network (None: the policy 0.6 / 256),
     judged by the byte model; returns (MHDCMatrix, result dict)."""
     n, rp, ci, v = _csr_args(rowptr, colind, val)

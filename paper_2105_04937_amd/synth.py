@@ -204,6 +204,78 @@ def batch_member(index: int, base_seed: int = 4000):
     return m, k
 
 
+def stencil_matrix_gpu(N: int, seed: int, points: int = 27, drop=0.0, extra_per_row: int = 0,
+                       diag_factor: float = 1.1, device="cuda"):
+    """Device-side generator of the same family as partially_diagonal()
+    (stencil couplings truncated at faces, per-octant or global drop
+    probability, extra uniform columns redrawn on collision, N(0,1) values,
+    diagonal = diag_factor * |row sum of off-diagonals|), drawn with a
+    torch generator seeded by `seed` on `device`.  Used where thousands of
+    matrices are needed (the selector's training and test sets); its stream
+    of random numbers differs from the numpy generator's.  Returns
+    (rowptr, colind, val) device tensors (int32, int32, float64)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = N * N * N
+    r = torch.arange(n, device=device, dtype=torch.int64)
+    ix, iy, iz = r % N, (r // N) % N, r // (N * N)
+    pts = stencil_points(points)
+    S = len(pts)
+    cols = torch.empty((n, S), dtype=torch.int64, device=device)
+    keep = torch.empty((n, S), dtype=torch.bool, device=device)
+    dpos = pts.index((0, 0, 0))
+    for s, (dx, dy, dz) in enumerate(pts):
+        cols[:, s] = r + dx + N * dy + N * N * dz
+        keep[:, s] = ((ix + dx >= 0) & (ix + dx < N) & (iy + dy >= 0) & (iy + dy < N)
+                      & (iz + dz >= 0) & (iz + dz < N))
+    if np.ndim(drop) == 0:
+        p_row = torch.full((n,), float(drop), device=device, dtype=torch.float64)
+    else:
+        h = N // 2
+        octant = 4 * (iz >= h).long() + 2 * (iy >= h).long() + (ix >= h).long()
+        p_row = torch.as_tensor(np.asarray(drop, np.float64), device=device)[octant]
+    del ix, iy, iz
+    u = torch.rand((n, S), generator=g, device=device, dtype=torch.float64)
+    dropped = u < p_row[:, None]
+    dropped[:, dpos] = False
+    keep &= ~dropped
+    del u, dropped
+    big = np.iinfo(np.int64).max
+    allc = torch.where(keep, cols, torch.full_like(cols, big))
+    del cols
+    if extra_per_row > 0:
+        extra = torch.randint(0, n, (n, extra_per_row), generator=g, device=device,
+                              dtype=torch.int64)
+        while True:
+            clash = torch.zeros((n, extra_per_row), dtype=torch.bool, device=device)
+            for e in range(extra_per_row):
+                clash[:, e] = (allc == extra[:, e:e + 1]).any(dim=1)
+                for f in range(e):
+                    clash[:, e] |= extra[:, f] == extra[:, e]
+            nb = int(clash.sum())
+            if nb == 0:
+                break
+            extra[clash] = torch.randint(0, n, (nb,), generator=g, device=device,
+                                         dtype=torch.int64)
+        allc = torch.cat([allc, extra], dim=1)
+        del extra
+    allc, _ = torch.sort(allc, dim=1)
+    valid = allc != big
+    counts = valid.sum(dim=1)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    colind = allc[valid]
+    rows = torch.repeat_interleave(torch.arange(n, device=device), counts)
+    del allc, valid
+    val = torch.randn(colind.numel(), generator=g, device=device, dtype=torch.float64)
+    is_diag = colind == rows
+    off = torch.where(is_diag, torch.zeros_like(val), val)
+    rs = torch.zeros(n, dtype=torch.float64, device=device).index_add_(0, rows, off)
+    val = torch.where(is_diag, diag_factor * rs.abs()[rows], val)
+    return rowptr.to(torch.int32), colind.to(torch.int32), val
+
+
 def vector(n: int, seed: int, k: int = 1) -> np.ndarray:
     """x ~ U[-1, 1]; shape (n,) for k == 1, else (n, k) column-major."""
     rng = np.random.default_rng([seed, 1])

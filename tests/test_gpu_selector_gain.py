@@ -1,0 +1,63 @@
+"""What the trained selector gains over the paper's policy.
+
+The committed network (trained on the GPU by the library's own kernels on
+2,000 matrices) decides (theta, n_b) for the 200 held-out matrices through
+mhdc_mlp_decide; each decision is looked up in the SpMV times measured on
+MI355X for the whole grid (committed with the data), after the byte-model
+judge that mhdc_select applies.  Compared with the exhaustive best of the
+grid and with the policy (theta = 0.6, n_b = 256; Sec. 6.4.3)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2105_04937_amd import learned
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+TEST = os.path.join(learned.DATA_DIR, "test_0000-0199.jsonl.gz")
+
+
+def test_selector_gain_over_policy():
+    recs = learned.load([TEST])
+    net = learned.load_network()
+    rep, rows = learned.evaluate(net, recs, tolerance=learned.JUDGE_TOLERANCE)
+    say("selector on %d held-out matrices: mean t/t_best %.4f (policy %.4f), within 5%%: %.3f "
+        "(policy %.3f), geomean speed-up over policy %.4f" % (
+            rep["matrices"], rep["mean_ratio_selected"], rep["mean_ratio_rule"],
+            rep["within_5pct_selected"], rep["within_5pct_rule"],
+            rep["geomean_speedup_over_rule"]))
+    assert rep["matrices"] == 200
+    # within 5% of exhaustive search on average, and better than the policy
+    assert rep["mean_ratio_selected"] <= 1.05
+    assert rep["mean_ratio_selected"] < rep["mean_ratio_rule"]
+    assert rep["within_5pct_selected"] > rep["within_5pct_rule"]
+    assert rep["geomean_speedup_over_rule"] > 1.0
+    # the decisions are those mhdc_select makes from the same network
+    ok = [r for r in rows if r["used_net"]]
+    assert len(ok) >= 150
+
+
+def test_select_end_to_end_with_trained_network():
+    """mhdc_select with the trained network: its decision equals the one
+    decided from the oracle's features, and the chosen handle's product is
+    bit-identical to the oracle's Fig. 16 kernel for that (theta, n_b)."""
+    import torch
+
+    import oracle
+    from oracle import selector as S
+    from paper_2105_04937_amd import mhdc, synth
+    from tests.gpu_helpers import assert_oracle_bits, dev
+    net = learned.load_network()
+    for seed, N in ((1, 40), (2, 56), (3, 72)):
+        m = synth.partially_diagonal(N, seed, drop=synth.OCTANT_DROP)
+        say("case: select end to end N=%d" % N)
+        d = dev(m)
+        h, r = mhdc.select(*d, model=net, tolerance=learned.JUDGE_TOLERANCE)
+        th, nb, ok = net.decide(torch.from_numpy(S.features(m.rowptr, m.colind, m.val)[None]).cuda())
+        assert (r["theta_net"], r["n_b_net"]) == (float(th[0]), int(nb[0]))
+        x = synth.vector(m.n, seed)
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, r["n_b"], r["theta"])
+        assert_oracle_bits(h.spmv(torch.from_numpy(x).cuda()), oracle.mhdc_spmv(ref, x),
+                           "selected theta=%g n_b=%d" % (r["theta"], r["n_b"]))
