@@ -94,19 +94,28 @@ typedef struct {
     int64_t R;           /* entries in the CSR part / remainder */
     double alpha, beta;
     double bytes_alg, bytes_paper, rp_est;
-    int32_t rows_per_lane, wg_size, xcd_remap; /* current launch shape */
+    int32_t rows_per_lane, wg_size, xcd_remap, csr_mode, rhs_group; /* launch shape */
 } mhdc_info;
 
 /* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
  * k = 1): rows each lane owns (spaced one wavefront apart); wg_size in
  * {64, 256};
  * xcd_remap != 0 maps workgroups so that each of the 8 XCDs walks one
- * contiguous range of row tiles.  Set before use, not while spmv calls on
- * the handle are in flight. */
+ * contiguous range of row tiles; csr_mode selects how the CSR part of a
+ * tile is processed: 1 = each staging lane multiplies its entries by the
+ * gathered x and stages the rounded products in LDS, 2 = values and columns
+ * are staged and each lane gathers x for its own rows, 0 = 1 for one
+ * right-hand side and 2 for several; rhs_group in {0, 1, 2, 4, 8, 16}:
+ * right-hand sides processed per pass over a tile (0 = all, up to 16; a
+ * further pass reads the tile's share of A again from the caches).  Every
+ * variant gives the same bits.  Set before use, not while spmv calls on the
+ * handle are in flight. */
 typedef struct {
     int32_t rows_per_lane;
     int32_t wg_size;
     int32_t xcd_remap;
+    int32_t csr_mode;
+    int32_t rhs_group;
 } mhdc_launch;
 
 /* M-HDC conversion (Sec. 4.3, Figs. 14-15), all steps in HIP kernels:

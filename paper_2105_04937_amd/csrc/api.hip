@@ -26,8 +26,8 @@ mhdc_launch default_launch(int32_t n, int32_t n_b)
     // the XCD-contiguous remap measured about 6% slower.
     const bool one_block = n_b >= n;
     if ((int64_t)n >= 256LL * 2 * 2048)
-        return mhdc_launch{(one_block || n_b % 128 == 0) ? 2 : 1, 256, 0};
-    return mhdc_launch{1, 64, 0};
+        return mhdc_launch{(one_block || n_b % 128 == 0) ? 2 : 1, 256, 0, 0, 0};
+    return mhdc_launch{1, 64, 0, 0, 0};
 }
 
 namespace {
@@ -60,6 +60,8 @@ void fill_info(const BdcMatrix &m, mhdc_info *o)
     o->rows_per_lane = m.launch.rows_per_lane;
     o->wg_size = m.launch.wg_size;
     o->xcd_remap = m.launch.xcd_remap;
+    o->csr_mode = m.launch.csr_mode;
+    o->rhs_group = m.launch.rhs_group;
 }
 
 int check_theta_nb(int32_t n, int32_t n_b, double theta, bool need_nb)

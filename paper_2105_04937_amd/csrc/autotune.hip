@@ -80,8 +80,12 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr, const int32_t *colin
     }
     k_fill_const<<<256, 256, 0, stream>>>(X, (int64_t)n * nrhs, 0.5);
 
-    static const mhdc_launch shapes[] = {{1, 64, 0}, {1, 256, 0}, {2, 256, 0}, {4, 256, 0},
-                                         {2, 256, 1}};
+    // launch shapes (rows per lane, lanes, XCD remap, CSR-part variant,
+    // right-hand sides per pass)
+    static const mhdc_launch shapes[] = {
+        {1, 64, 0, 0, 0},  {1, 256, 0, 0, 0}, {2, 256, 0, 0, 0}, {4, 256, 0, 0, 0},
+        {2, 256, 1, 0, 0}, {1, 256, 0, 1, 0}, {1, 256, 0, 2, 0}, {2, 256, 0, 2, 0},
+        {1, 256, 0, 0, 4}, {2, 256, 0, 0, 4}};
     mhdc_handle best = nullptr;
     mhdc_tune_result res{};
     res.us = 1e30f;
@@ -94,7 +98,7 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr, const int32_t *colin
         }
         bool keep = false;
         for (const mhdc_launch &shp : shapes) {
-            if (shp.rows_per_lane == 4 && nrhs > 1)
+            if ((shp.rows_per_lane == 4 && nrhs > 1) || (shp.rhs_group && shp.rhs_group >= nrhs))
                 continue;
             h->m.launch = shp;
             float us = 0;

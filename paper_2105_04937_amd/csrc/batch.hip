@@ -26,19 +26,45 @@ struct BatchItem {
     SpmvArgs a;
     int64_t tile_begin;  // first global tile number of this item
     int32_t kc;          // accumulator width class (1, 2, 4, 8, 16)
-    int32_t pad;
+    int32_t rg;          // CSR part: stage values/columns (1) or products (0)
 };
+
+template <int WG, int KC>
+constexpr int lds_of()
+{
+    return std::max(TileShape<WG, KC, false>::LDS_BYTES, TileShape<WG, KC, true>::LDS_BYTES);
+}
+
+// Right-hand sides per pass over a tile in the persistent kernel (larger
+// items take several passes).  One pass of up to 16 measured faster than
+// passes of 4 despite the larger register budget: every further pass reads
+// the tile's share of A again.
+constexpr int BATCH_MAX_KC = 16;
+#ifndef BATCH_RG_FOR_MANY
+#define BATCH_RG_FOR_MANY 1
+#endif
 
 template <int WG>
 constexpr int batch_lds_doubles()
 {
-    int m = 1;
-    m = std::max(m, 1 * TileShape<WG, 1>::CH);
-    m = std::max(m, 2 * TileShape<WG, 2>::CH);
-    m = std::max(m, 4 * TileShape<WG, 4>::CH);
-    m = std::max(m, 8 * TileShape<WG, 8>::CH);
-    m = std::max(m, 16 * TileShape<WG, 16>::CH);
-    return m;
+    int m = 8;
+    m = std::max(m, lds_of<WG, 1>());
+    m = std::max(m, lds_of<WG, 2>());
+    m = std::max(m, lds_of<WG, 4>());
+    m = std::max(m, lds_of<WG, 8>());
+    m = std::max(m, lds_of<WG, 16>());
+    return (m + 7) / 8;
+}
+
+// One right-hand side: either CSR-part variant; several: values/columns
+// staged (the product variant's LDS grows with the number of columns).
+template <int WG, int KC>
+__device__ inline void batch_tile(const BatchItem &it, int64_t local, double *lds)
+{
+    if (BATCH_RG_FOR_MANY && (KC > 1 || it.rg))
+        spmv_tile<WG, 1, KC, true, true>(it.a, local, lds);
+    else
+        spmv_tile<WG, 1, KC, true, false>(it.a, local, lds);
 }
 
 __global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
@@ -69,11 +95,11 @@ __global__ __launch_bounds__(WG) void k_batch(const BatchItem *__restrict__ item
         const BatchItem &it = items[lo];
         const int64_t local = t - it.tile_begin;
         switch (it.kc) {
-        case 1: spmv_tile<WG, 1, 1, true>(it.a, local, s_prod); break;
-        case 2: spmv_tile<WG, 1, 2, true>(it.a, local, s_prod); break;
-        case 4: spmv_tile<WG, 1, 4, true>(it.a, local, s_prod); break;
-        case 8: spmv_tile<WG, 1, 8, true>(it.a, local, s_prod); break;
-        default: spmv_tile<WG, 1, 16, true>(it.a, local, s_prod); break;
+        case 1: batch_tile<WG, 1>(it, local, s_prod); break;
+        case 2: batch_tile<WG, 2>(it, local, s_prod); break;
+        case 4: batch_tile<WG, 4>(it, local, s_prod); break;
+        case 8: batch_tile<WG, 8>(it, local, s_prod); break;
+        default: batch_tile<WG, 16>(it, local, s_prod); break;
         }
     }
 }
@@ -135,7 +161,8 @@ int upload_items(mhdc_batch_s *b, const double *const *X, const int64_t *ldx, do
             return rc;
         BatchItem &it = b->host_items[i];
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
-        it.kc = kc_for(k);
+        it.kc = kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
+        it.rg = row_gather(m.launch.csr_mode, it.kc) ? 1 : 0;
         it.tile_begin = tiles;
         tiles += ((int64_t)m.n + b->wg - 1) / b->wg;
         flops += 2.0 * (double)m.nnz * k;

@@ -30,7 +30,7 @@ struct BdcMatrix {
     int32_t *rem_col = nullptr;  // [R]
     double *rem_val = nullptr;   // [R]
     int device = 0;
-    mhdc_launch launch{2, 256, 1};
+    mhdc_launch launch{2, 256, 0, 0, 0};
 };
 
 // Thread-local error state.
@@ -66,6 +66,7 @@ struct SpmvArgs;
 SpmvArgs make_args(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
                    int32_t k, int32_t v);
 int kc_for(int k);
+bool row_gather(int32_t csr_mode, int kc);
 int check_operands(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
                    int64_t ldy, int32_t k);
 int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y,

@@ -6,51 +6,60 @@
 namespace mhdc {
 namespace {
 
-template <int WG, int V, int KC, bool HAS_REM>
+template <int WG, int V, int KC, bool HAS_REM, bool RG>
 __global__ __launch_bounds__(WG) void k_spmv(SpmvArgs a)
 {
-    __shared__ double s_prod[HAS_REM ? KC * TileShape<WG, KC>::CH : 1];
+    __shared__ double s_lds[HAS_REM ? (TileShape<WG, KC, RG>::LDS_BYTES + 7) / 8 : 1];
     const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    spmv_tile<WG, V, KC, HAS_REM>(a, tile, s_prod);
+    spmv_tile<WG, V, KC, HAS_REM, RG>(a, tile, s_lds);
 }
 
 using KernelFn = void (*)(SpmvArgs);
 
 template <int WG, int V, int KC>
-KernelFn pick_rem(bool has_rem)
+KernelFn pick_rem(bool has_rem, bool rg)
 {
-    return has_rem ? (KernelFn)k_spmv<WG, V, KC, true> : (KernelFn)k_spmv<WG, V, KC, false>;
+    if (!has_rem)
+        return (KernelFn)k_spmv<WG, V, KC, false, false>;
+    return rg ? (KernelFn)k_spmv<WG, V, KC, true, true> : (KernelFn)k_spmv<WG, V, KC, true, false>;
 }
 
 template <int WG, int V>
-KernelFn pick_kc(int kc, bool has_rem)
+KernelFn pick_kc(int kc, bool has_rem, bool rg)
 {
     switch (kc) {
-    case 1: return pick_rem<WG, V, 1>(has_rem);
-    case 2: return pick_rem<WG, V, 2>(has_rem);
-    case 4: return pick_rem<WG, V, 4>(has_rem);
-    case 8: return pick_rem<WG, V, 8>(has_rem);
-    case 16: return pick_rem<WG, V, 16>(has_rem);
+    case 1: return pick_rem<WG, V, 1>(has_rem, rg);
+    case 2: return pick_rem<WG, V, 2>(has_rem, rg);
+    case 4: return pick_rem<WG, V, 4>(has_rem, rg);
+    case 8: return pick_rem<WG, V, 8>(has_rem, rg);
+    case 16: return pick_rem<WG, V, 16>(has_rem, rg);
     }
     return nullptr;
 }
 
 template <int WG>
-KernelFn pick_v(int v, int kc, bool has_rem)
+KernelFn pick_v(int v, int kc, bool has_rem, bool rg)
 {
     switch (v) {
-    case 1: return pick_kc<WG, 1>(kc, has_rem);
-    case 2: return kc <= 4 ? pick_kc<WG, 2>(kc, has_rem) : nullptr;
-    case 4: return kc == 1 ? pick_rem<WG, 4, 1>(has_rem) : nullptr;
+    case 1: return pick_kc<WG, 1>(kc, has_rem, rg);
+    case 2:
+        if (kc == 1)
+            return pick_rem<WG, 2, 1>(has_rem, rg);
+        if (kc == 2)
+            return pick_rem<WG, 2, 2>(has_rem, rg);
+        if (kc == 4)
+            return pick_rem<WG, 2, 4>(has_rem, rg);
+        return nullptr;
+    case 4: return kc == 1 ? pick_rem<WG, 4, 1>(has_rem, rg) : nullptr;
     }
     return nullptr;
 }
 
-KernelFn pick(int wg, int v, int kc, bool has_rem)
+KernelFn pick(int wg, int v, int kc, bool has_rem, bool rg)
 {
     switch (wg) {
-    case 64: return pick_v<64>(v, kc, has_rem);
-    case 256: return pick_v<256>(v, kc, has_rem);
+    case 64: return pick_v<64>(v, kc, has_rem, rg);
+    case 256: return pick_v<256>(v, kc, has_rem, rg);
     }
     return nullptr;
 }
@@ -67,6 +76,11 @@ __global__ __launch_bounds__(256) void k_zero_cols(double *Y, int64_t ldy, int32
 
 }  // namespace
 
+bool row_gather(int32_t csr_mode, int kc)
+{
+    return csr_mode == 2 || (csr_mode == 0 && kc > 1);
+}
+
 int kc_for(int k)
 {
     return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
@@ -78,6 +92,11 @@ int check_launch(const mhdc_launch &cfg)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "wg_size must be 64 or 256");
     if (cfg.rows_per_lane != 1 && cfg.rows_per_lane != 2 && cfg.rows_per_lane != 4)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "rows_per_lane must be 1, 2 or 4");
+    if (cfg.csr_mode < 0 || cfg.csr_mode > 2)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "csr_mode must be 0, 1 or 2");
+    const int g = cfg.rhs_group;
+    if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "rhs_group must be 0, 1, 2, 4, 8 or 16");
     return MHDC_OK;
 }
 
@@ -131,7 +150,8 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
     if (rc || m.n == 0)
         return rc;
     int32_t v = m.launch.rows_per_lane, wg = m.launch.wg_size;
-    const int kc = kc_for(k);
+    const int group = m.launch.rhs_group > 0 ? m.launch.rhs_group : 16;
+    const int kc = kc_for(k < group ? k : group);
     // registers: 4 rows per lane only for one right-hand side, 2 up to four
     if (kc >= 8)
         v = 1;
@@ -145,7 +165,7 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
         k_zero_cols<<<dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, stream>>>(Y, ldy, m.n,
                                                                                       k);
     } else {
-        KernelFn fn = pick(wg, v, kc, has_rem);
+        KernelFn fn = pick(wg, v, kc, has_rem, row_gather(m.launch.csr_mode, kc));
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, v);

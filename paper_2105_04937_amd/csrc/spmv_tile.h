@@ -13,7 +13,7 @@
 //                      where 0 <= i + off_k < n,
 // and stores acc once.  Every product is rounded before it is added (no fused
 // multiply-add), so a row's value is bit-identical to the sequential kernels
-// of Figs. 3, 8 and 16 and does not depend on the launch shape.
+// of Figs. 3, 8 and 16 and does not depend on the launch shape or variant.
 //
 // Work mapping (gfx950, 64-lane wavefronts):
 //   * a workgroup of WG lanes owns a tile of WG*V consecutive rows; lane l of
@@ -26,10 +26,15 @@
 //   * when all rows of a wavefront fall in one block the block's diagonal
 //     range and offsets are wave-uniform; diagonals are processed U at a time
 //     so that U*V value loads and U*V x loads are in flight per lane;
-//   * the tile's remainder entries are contiguous: each chunk is read with
-//     coalesced loads, multiplied by the gathered x on the spot (CH/WG
-//     independent gathers per lane) and the products are staged in LDS; each
-//     lane then sums its own rows' products from LDS in column order.
+//   * the tile's remainder entries are contiguous and read in chunks with
+//     coalesced loads into LDS.  Two variants (RG):
+//       RG = false: the staging lane multiplies its entries by the gathered
+//         x on the spot (CH/WG independent gathers per lane) and stages the
+//         rounded products; each lane then adds its rows' products;
+//       RG = true: values and columns are staged (12 bytes per entry, for
+//         any number of right-hand sides) and each lane gathers x for its
+//         own rows' entries -- for rows of similar structure (stencils) the
+//         lanes of a wavefront then read neighbouring x.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,22 +72,29 @@ __device__ inline int xcd_tile(int w, int G)
     return x * q + (x < r ? x : r) + idx;
 }
 
-template <int WG, int KC>
+template <int WG, int KC, bool RG>
 struct TileShape {
-    // remainder entries staged per chunk; LDS = KC * CH doubles
-    static constexpr int CH = (WG * 8 / KC) < WG ? WG : WG * 8 / KC;
+    // remainder entries staged per chunk
+    static constexpr int CH = RG ? WG * 8 : ((WG * 8 / KC) < WG ? WG : WG * 8 / KC);
+    static constexpr int LDS_BYTES = RG ? CH * 12 : KC * CH * 8;
     // diagonals processed together in the uniform DIA path
     static constexpr int U = KC == 1 ? 4 : (KC <= 4 ? 2 : 1);
+    // remainder entries gathered together per row in the RG variant
+    static constexpr int UR = KC == 1 ? 4 : (KC <= 4 ? 2 : 1);
 };
 
-template <int WG, int V, int KC, bool HAS_REM>
-__device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod)
+template <int WG, int V, int KC, bool HAS_REM, bool RG>
+__device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds,
+                                      const double *__restrict__ Xg, double *__restrict__ Yg,
+                                      int32_t kc_n)
 {
     // products are rounded before they are added: no multiply-add fusion
 #pragma clang fp contract(off)
+    using Shape = TileShape<WG, KC, RG>;
     constexpr int T = WG * V;
-    constexpr int CH = TileShape<WG, KC>::CH;
-    constexpr int U = TileShape<WG, KC>::U;
+    constexpr int CH = Shape::CH;
+    constexpr int U = Shape::U;
+    constexpr int UR = Shape::UR;
     const int n = a.n;
     const int64_t tile_base = tile * T;
     const int lane = threadIdx.x & 63;
@@ -108,6 +120,8 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                 rs[v] = row < n ? a.rem_ptr[row] : 0;
                 re[v] = row < n ? a.rem_ptr[row + 1] : 0;
             }
+            double *s_val = static_cast<double *>(lds);
+            int32_t *s_col = reinterpret_cast<int32_t *>(s_val + CH);
             for (int32_t cb = e_beg; cb < e_end; cb += CH) {
                 const int32_t ce = cb + CH < e_end ? cb + CH : e_end;
 #pragma unroll
@@ -116,10 +130,15 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                     if (e < ce) {
                         const double w = __builtin_nontemporal_load(a.rem_val + e);
                         const int32_t c = __builtin_nontemporal_load(a.rem_col + e);
+                        if constexpr (RG) {
+                            s_val[e - cb] = w;
+                            s_col[e - cb] = c;
+                        } else {
 #pragma unroll
-                        for (int r = 0; r < KC; r++)
-                            if (r < a.k)
-                                s_prod[r * CH + (e - cb)] = __dmul_rn(w, a.X[r * a.ldx + c]);
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n)
+                                    s_val[r * CH + (e - cb)] = __dmul_rn(w, Xg[r * a.ldx + c]);
+                        }
                     }
                 }
                 __syncthreads();
@@ -127,11 +146,40 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                 for (int v = 0; v < V; v++) {
                     const int32_t lo = rs[v] > cb ? rs[v] : cb;
                     const int32_t hi = re[v] < ce ? re[v] : ce;
-                    for (int32_t e = lo; e < hi; e++)
+                    if constexpr (RG) {
+                        int32_t e = lo;
+                        for (; e + UR <= hi; e += UR) {
+                            double w[UR], xv[UR][KC];
 #pragma unroll
-                        for (int r = 0; r < KC; r++)
-                            if (r < a.k)
-                                acc[v][r] = __dadd_rn(acc[v][r], s_prod[r * CH + (e - cb)]);
+                            for (int u = 0; u < UR; u++) {
+                                w[u] = s_val[e + u - cb];
+                                const int32_t c = s_col[e + u - cb];
+#pragma unroll
+                                for (int r = 0; r < KC; r++)
+                                    xv[u][r] = r < kc_n ? Xg[r * a.ldx + c] : 0.0;
+                            }
+#pragma unroll
+                            for (int u = 0; u < UR; u++)
+#pragma unroll
+                                for (int r = 0; r < KC; r++)
+                                    if (r < kc_n)
+                                        acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w[u], xv[u][r]));
+                        }
+                        for (; e < hi; e++) {
+                            const double w = s_val[e - cb];
+                            const int32_t c = s_col[e - cb];
+#pragma unroll
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n)
+                                    acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w, Xg[r * a.ldx + c]));
+                        }
+                    } else {
+                        for (int32_t e = lo; e < hi; e++)
+#pragma unroll
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n)
+                                    acc[v][r] = __dadd_rn(acc[v][r], s_val[r * CH + (e - cb)]);
+                    }
                 }
                 __syncthreads();
             }
@@ -170,8 +218,8 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                             w[u][v] = __builtin_nontemporal_load(seg + v * 64 + lane);
 #pragma unroll
                             for (int r = 0; r < KC; r++)
-                                if (r < a.k)
-                                    xv[u][v][r] = a.X[r * a.ldx + j];
+                                if (r < kc_n)
+                                    xv[u][v][r] = Xg[r * a.ldx + j];
                         }
                     }
                 }
@@ -182,10 +230,12 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                         if (in[u][v])
 #pragma unroll
                             for (int r = 0; r < KC; r++)
-                                if (r < a.k)
+                                if (r < kc_n)
                                     acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w[u][v], xv[u][v][r]));
             }
         } else {
+            // Rows of one wavefront span several blocks: each row walks its
+            // own block's list, two diagonals at a time.
 #pragma unroll
             for (int v = 0; v < V; v++) {
                 const int64_t row = wave_base + v * 64 + lane;
@@ -193,15 +243,46 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
                     const int64_t ib = row / a.n_b;
                     const int64_t t = row - ib * a.n_b;
                     const int32_t kb0 = a.dia_ptr[ib], kb1 = a.dia_ptr[ib + 1];
-                    for (int32_t kk = kb0; kk < kb1; kk++) {
+                    int32_t kk = kb0;
+                    for (; kk + 2 <= kb1; kk += 2) {
+                        const int64_t j0 = row + a.dia_off[kk], j1 = row + a.dia_off[kk + 1];
+                        const bool in0 = j0 >= 0 && j0 < n, in1 = j1 >= 0 && j1 < n;
+                        double w0 = 0.0, w1 = 0.0, x0[KC], x1[KC];
+#pragma unroll
+                        for (int r = 0; r < KC; r++)
+                            x0[r] = x1[r] = 0.0;
+                        if (in0) {
+                            w0 = __builtin_nontemporal_load(a.dia_val + (int64_t)kk * a.n_b + t);
+#pragma unroll
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n)
+                                    x0[r] = Xg[r * a.ldx + j0];
+                        }
+                        if (in1) {
+                            w1 = __builtin_nontemporal_load(a.dia_val + (int64_t)(kk + 1) * a.n_b + t);
+#pragma unroll
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n)
+                                    x1[r] = Xg[r * a.ldx + j1];
+                        }
+#pragma unroll
+                        for (int r = 0; r < KC; r++)
+                            if (r < kc_n) {
+                                if (in0)
+                                    acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w0, x0[r]));
+                                if (in1)
+                                    acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w1, x1[r]));
+                            }
+                    }
+                    if (kk < kb1) {
                         const int64_t j = row + a.dia_off[kk];
                         if (j >= 0 && j < n) {
                             const double w =
                                 __builtin_nontemporal_load(a.dia_val + (int64_t)kk * a.n_b + t);
 #pragma unroll
                             for (int r = 0; r < KC; r++)
-                                if (r < a.k)
-                                    acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w, a.X[r * a.ldx + j]));
+                                if (r < kc_n)
+                                    acc[v][r] = __dadd_rn(acc[v][r], __dmul_rn(w, Xg[r * a.ldx + j]));
                         }
                     }
                 }
@@ -215,9 +296,21 @@ __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, double *s_prod
         if (row < n) {
 #pragma unroll
             for (int r = 0; r < KC; r++)
-                if (r < a.k)
-                    __builtin_nontemporal_store(acc[v][r], a.Y + r * a.ldy + row);
+                if (r < kc_n)
+                    __builtin_nontemporal_store(acc[v][r], Yg + r * a.ldy + row);
         }
+    }
+}
+
+// All right-hand sides of the tile, KC columns per pass (the tile's share
+// of A is read again from the caches for every further pass).
+template <int WG, int V, int KC, bool HAS_REM, bool RG>
+__device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, void *lds)
+{
+    for (int32_t r0 = 0; r0 < a.k; r0 += KC) {
+        const int32_t kc_n = a.k - r0 < KC ? a.k - r0 : KC;
+        spmv_tile_cols<WG, V, KC, HAS_REM, RG>(a, tile, lds, a.X + r0 * a.ldx, a.Y + r0 * a.ldy,
+                                               kc_n);
     }
 }
 

@@ -34,7 +34,8 @@ class Info(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("bytes_alg", ctypes.c_double), ("bytes_paper", ctypes.c_double),
                 ("rp_est", ctypes.c_double), ("rows_per_lane", ctypes.c_int32),
-                ("wg_size", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+                ("wg_size", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("csr_mode", ctypes.c_int32), ("rhs_group", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -42,7 +43,8 @@ class Info(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("wg_size", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("csr_mode", ctypes.c_int32),
+                ("rhs_group", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -193,8 +195,8 @@ class _Matrix:
         _check(self._fn("get_info")(self._h, ctypes.byref(out)))
         return out.as_dict()
 
-    def set_launch(self, rows_per_lane=2, wg_size=256, xcd_remap=1):
-        cfg = Launch(rows_per_lane, wg_size, xcd_remap)
+    def set_launch(self, rows_per_lane=2, wg_size=256, xcd_remap=0, csr_mode=0, rhs_group=0):
+        cfg = Launch(rows_per_lane, wg_size, xcd_remap, csr_mode, rhs_group)
         _check(self._fn("set_launch")(self._h, ctypes.byref(cfg)))
         return self
 
@@ -353,7 +355,8 @@ def autotune(rowptr, colind, val, theta: float, nrhs: int = 1,
     if not h:
         _raise()
     out = dict(n_b=res.n_b, us=res.us, tried=res.tried,
-               launch=(res.launch.rows_per_lane, res.launch.wg_size, res.launch.xcd_remap))
+               launch=(res.launch.rows_per_lane, res.launch.wg_size, res.launch.xcd_remap,
+                       res.launch.csr_mode, res.launch.rhs_group))
     return MHDCMatrix(h, n), out
 
 

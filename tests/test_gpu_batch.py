@@ -126,7 +126,8 @@ def test_autotune(k):
     assert res["n_b"] in cands and res["tried"] >= len(cands) * 3 and res["us"] > 0
     inf = h.info()
     assert inf["n_b"] == res["n_b"]
-    assert (inf["rows_per_lane"], inf["wg_size"], inf["xcd_remap"]) == res["launch"]
+    assert (inf["rows_per_lane"], inf["wg_size"], inf["xcd_remap"], inf["csr_mode"],
+            inf["rhs_group"]) == res["launch"]
     ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, res["n_b"], 0.6)
     X = np.ascontiguousarray(np.random.default_rng(k).uniform(-1, 1, size=(k, m.n)))
     Y = h.spmm(torch.from_numpy(X).cuda()).cpu().numpy()

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 THETAS = [0.0, 0.5, 0.6, 2.0 / 3.0, 0.75, 1.0]
 SHAPES = [(1, 64, 0), (1, 64, 1), (2, 64, 1), (4, 64, 1), (1, 256, 1), (2, 256, 0),
-          (2, 256, 1), (4, 256, 1)]
+          (2, 256, 1), (4, 256, 1), (1, 256, 0, 2), (2, 256, 0, 2), (1, 64, 0, 2, 0),
+          (2, 256, 0, 1, 0)]
 
 
 def _example_csr():
@@ -144,7 +145,8 @@ def test_multi_rhs(k):
             oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 14, 0.6),
             oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6), None]
     for mat, ref in zip(mats, refs):
-        for shp in ((1, 64, 1), (2, 256, 1), (4, 256, 0)):
+        for shp in ((1, 64, 1), (2, 256, 1), (4, 256, 0), (1, 256, 0, 1, 0), (1, 256, 0, 2, 0),
+                    (1, 256, 0, 0, 4), (2, 256, 0, 2, 2), (1, 64, 0, 1, 1)):
             mat.set_launch(*shp)
             Y = mat.spmm(Xd).cpu().numpy()
             for r in range(k):
