@@ -189,7 +189,9 @@ void csr_destroy(csr_handle h);
 /* -------------------------------------------------- memory benchmark */
 /* The two memory benchmark kernels of Sec. 6.2 (Figs. 19-20):
  * direct C[i] += A[i]*B[i] (32 bytes per element) and indirect
- * C[i] += A[i]*B[I[i]] (36 bytes per element).  Asynchronous. */
+ * C[i] += A[i]*B[I[i]] (36 bytes per element), the product rounded before
+ * the add.  All arrays hold N elements; an index I[i] outside [0, N) leaves
+ * C[i] unchanged.  Asynchronous. */
 int mhdc_stream_direct(int64_t N, const double *A, const double *B,
                        double *C, hipStream_t stream);
 int mhdc_stream_indirect(int64_t N, const double *A, const double *B,

@@ -62,9 +62,9 @@ template <int WG, int KC>
 __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *lds)
 {
     if (BATCH_RG_FOR_MANY && (KC > 1 || it.rg))
-        spmv_tile<WG, 1, KC, true, true>(it.a, local, lds);
+        spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);
     else
-        spmv_tile<WG, 1, KC, true, false>(it.a, local, lds);
+        spmv_tile<WG, 1, KC, true, true, false>(it.a, local, lds);
 }
 
 __global__ void k_batch_reset(int32_t *counter) { *counter = 0; }

@@ -6,60 +6,67 @@
 namespace mhdc {
 namespace {
 
-template <int WG, int V, int KC, bool HAS_REM, bool RG>
+template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
 __global__ __launch_bounds__(WG) void k_spmv(SpmvArgs a)
 {
     __shared__ double s_lds[HAS_REM ? (TileShape<WG, KC, RG>::LDS_BYTES + 7) / 8 : 1];
     const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    spmv_tile<WG, V, KC, HAS_REM, RG>(a, tile, s_lds);
+    spmv_tile<WG, V, KC, HAS_DIA, HAS_REM, RG>(a, tile, s_lds);
 }
 
 using KernelFn = void (*)(SpmvArgs);
 
+// parts: 1 = DIA part, 2 = CSR part, 4 = CSR part with staged values/columns
 template <int WG, int V, int KC>
-KernelFn pick_rem(bool has_rem, bool rg)
+KernelFn pick_rem(int parts)
 {
-    if (!has_rem)
-        return (KernelFn)k_spmv<WG, V, KC, false, false>;
-    return rg ? (KernelFn)k_spmv<WG, V, KC, true, true> : (KernelFn)k_spmv<WG, V, KC, true, false>;
+    switch (parts) {
+    case 1:
+    case 5: return (KernelFn)k_spmv<WG, V, KC, true, false, false>;
+    case 3: return (KernelFn)k_spmv<WG, V, KC, true, true, false>;
+    case 7: return (KernelFn)k_spmv<WG, V, KC, true, true, true>;
+    case 2: return (KernelFn)k_spmv<WG, V, KC, false, true, false>;
+    case 6: return (KernelFn)k_spmv<WG, V, KC, false, true, true>;
+    }
+    return nullptr;
 }
 
 template <int WG, int V>
-KernelFn pick_kc(int kc, bool has_rem, bool rg)
+KernelFn pick_kc(int kc, int parts)
 {
     switch (kc) {
-    case 1: return pick_rem<WG, V, 1>(has_rem, rg);
-    case 2: return pick_rem<WG, V, 2>(has_rem, rg);
-    case 4: return pick_rem<WG, V, 4>(has_rem, rg);
-    case 8: return pick_rem<WG, V, 8>(has_rem, rg);
-    case 16: return pick_rem<WG, V, 16>(has_rem, rg);
+    case 1: return pick_rem<WG, V, 1>(parts);
+    case 2: return pick_rem<WG, V, 2>(parts);
+    case 4: return pick_rem<WG, V, 4>(parts);
+    case 8: return pick_rem<WG, V, 8>(parts);
+    case 16: return pick_rem<WG, V, 16>(parts);
     }
     return nullptr;
 }
 
 template <int WG>
-KernelFn pick_v(int v, int kc, bool has_rem, bool rg)
+KernelFn pick_v(int v, int kc, int parts)
 {
     switch (v) {
-    case 1: return pick_kc<WG, 1>(kc, has_rem, rg);
+    case 1: return pick_kc<WG, 1>(kc, parts);
     case 2:
         if (kc == 1)
-            return pick_rem<WG, 2, 1>(has_rem, rg);
+            return pick_rem<WG, 2, 1>(parts);
         if (kc == 2)
-            return pick_rem<WG, 2, 2>(has_rem, rg);
+            return pick_rem<WG, 2, 2>(parts);
         if (kc == 4)
-            return pick_rem<WG, 2, 4>(has_rem, rg);
+            return pick_rem<WG, 2, 4>(parts);
         return nullptr;
-    case 4: return kc == 1 ? pick_rem<WG, 4, 1>(has_rem, rg) : nullptr;
+    case 4: return kc == 1 ? pick_rem<WG, 4, 1>(parts) : nullptr;
     }
     return nullptr;
 }
 
-KernelFn pick(int wg, int v, int kc, bool has_rem, bool rg)
+KernelFn pick(int wg, int v, int kc, int parts)
 {
     switch (wg) {
-    case 64: return pick_v<64>(v, kc, has_rem, rg);
-    case 256: return pick_v<256>(v, kc, has_rem, rg);
+    case 64: return pick_v<64>(v, kc, parts);
+    case 256: return pick_v<256>(v, kc, parts);
     }
     return nullptr;
 }
@@ -165,7 +172,9 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
         k_zero_cols<<<dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, stream>>>(Y, ldy, m.n,
                                                                                       k);
     } else {
-        KernelFn fn = pick(wg, v, kc, has_rem, row_gather(m.launch.csr_mode, kc));
+        const int parts = (has_dia ? 1 : 0) | (has_rem ? 2 : 0) |
+                          (row_gather(m.launch.csr_mode, kc) ? 4 : 0);
+        KernelFn fn = pick(wg, v, kc, parts);
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, v);

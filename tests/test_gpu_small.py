@@ -282,15 +282,23 @@ def test_allocation_failure_leaks_nothing():
     assert torch.cuda.mem_get_info()[0] >= free0 - (4 << 20)
 
 
-def test_memory_benchmark_kernels():
-    say("case: memory benchmark kernels")
-    N = 100_003
-    rng = np.random.default_rng(0)
-    A, B, C = rng.random(N), rng.random(N), rng.random(N)
-    I = np.arange(N, dtype=np.int32)
-    Ad, Bd, Cd, Id = (torch.from_numpy(t).cuda() for t in (A, B, C, I))
-    mhdc.stream_direct(Ad, Bd, Cd)
-    assert np.allclose(Cd.cpu().numpy(), oracle.stream_direct(A, B, C), rtol=1e-15, atol=0)
-    Cd2 = torch.from_numpy(C).cuda()
-    mhdc.stream_indirect(Ad, Bd, Id, Cd2)
-    assert np.allclose(Cd2.cpu().numpy(), oracle.stream_indirect(A, B, I, C), rtol=1e-15, atol=0)
+@pytest.mark.parametrize("N,shift", [(100_003, 0), (100_000, 0), (1, 0), (2, 0), (4097, 1)])
+def test_memory_benchmark_kernels(N, shift):
+    """Sec. 6.2 kernels, bit-exact against the sequential loops; odd N and a
+    view shifted by one element (8-byte aligned only) take the scalar path."""
+    say("case: memory benchmark kernels N=%d shift=%d" % (N, shift))
+    rng = np.random.default_rng(N)
+    A, B, C = (rng.random(N + shift) for _ in range(3))
+    I = rng.permutation(N + shift).astype(np.int32)
+    I[I >= N] = 0
+    Ad, Bd, Id = (torch.from_numpy(t).cuda()[shift:] for t in (A, B, I))
+    Cd = torch.from_numpy(C).cuda()[shift:]
+    mhdc.stream_direct(Ad.contiguous() if shift == 0 else Ad, Bd, Cd)
+    want = oracle.stream_direct(A[shift:], B[shift:], C[shift:])
+    assert np.array_equal(Cd.cpu().numpy(), want)
+    Cd2 = torch.from_numpy(C).cuda()[shift:]
+    Ii = I[shift:].copy()
+    Ii[Ii >= N] = 0
+    mhdc.stream_indirect(Ad, Bd, torch.from_numpy(Ii).cuda(), Cd2)
+    assert np.array_equal(Cd2.cpu().numpy(), oracle.stream_indirect(A[shift:], B[shift:], Ii,
+                                                                    C[shift:]))
