@@ -77,13 +77,16 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def kernel_traffic():
+def kernel_traffic(launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different version of the kernel source."""
+    None when absent or taken on a different version of the kernel source or
+    another launch shape."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
         if rec.get("spmv_source_sha256") != kernel_source_sha256():
+            return None
+        if list(rec.get("launch", [])) != list(launch):
             return None
         return rec.get("bytes_per_launch")
     except (OSError, ValueError):
@@ -170,6 +173,7 @@ def main():
         lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, args.n_b, args.theta), x, args.steps,
         args.warmup, stream, "M-HDC")
     t_pp = paper_protocol(lambda: h.spmv(x, y, stream), 100, 5, stream)
+    launch = [inf[f] for f in ("rows_per_lane", "wg_size", "xcd_remap", "csr_mode", "rhs_group")]
     out = {}
     if not args.only_mhdc:
         hd, _, t_hdc, conv_hdc, inf_h = run_format(
@@ -254,11 +258,11 @@ def main():
         "config": {"workload": "heptadiagonal 7-point 256^3 (n=%d, nnz=%d), M-HDC n_b=%d "
                                "theta=%.2f" % (m.n, m.nnz, args.n_b, args.theta),
                    "n": m.n, "nnz": m.nnz, "n_b": args.n_b, "theta": args.theta,
-                   "launch": [inf["rows_per_lane"], inf["wg_size"], inf["xcd_remap"]]},
+                   "launch": launch},
         "hbm_gb_per_s": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": kernel_traffic()},
+                     "traffic": kernel_traffic(launch)},
         "bytes_alg_per_launch": inf["bytes_alg"],
         "bytes_paper_model": inf["bytes_paper"],
         "paper_protocol_us": round(t_pp * 1e6, 2),

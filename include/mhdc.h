@@ -100,8 +100,10 @@ typedef struct {
 /* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
  * k = 1): rows each lane owns (spaced one wavefront apart); wg_size in
  * {64, 256};
- * xcd_remap != 0 maps workgroups so that each of the 8 XCDs walks one
- * contiguous range of row tiles; csr_mode selects how the CSR part of a
+ * xcd_remap (0 or a power of two up to 64) places row tiles on the 8 XCDs:
+ * 0 = dispatch order (tile w on XCD w mod 8), 1 = each XCD walks one
+ * contiguous eighth of the tiles, C >= 2 = runs of C consecutive tiles per
+ * XCD, the XCDs taking the runs in turn; csr_mode selects how the CSR part of a
  * tile is processed: 1 = each staging lane multiplies its entries by the
  * gathered x and stages the rounded products in LDS, 2 = values and columns
  * are staged and each lane gathers x for its own rows, 0 = 1 for one

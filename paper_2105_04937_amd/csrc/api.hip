@@ -22,11 +22,16 @@ mhdc_launch default_launch(int32_t n, int32_t n_b)
     // 128 rows stay inside one block (n_b a multiple of 128, or one block),
     // else 1 so that n_b = 64, 192, ... keep the wave-uniform diagonal path.
     // Small matrices: 64-lane workgroups so that the 256 CUs get work.
-    // Dispatch order is kept (xcd_remap = 0): on the 256^3 heptadiagonal case
-    // the XCD-contiguous remap measured about 6% slower.
+    // Runs of 4096 consecutive rows per XCD (xcd_remap 8 or 16 tiles): a
+    // tile's neighbours, whose x entries it also reads through the near
+    // diagonals, then share its L2.  On the 256^3 heptadiagonal case this
+    // measured 2-4% faster than dispatch order; one contiguous eighth per
+    // XCD (xcd_remap = 1) measured 5% slower.
     const bool one_block = n_b >= n;
-    if ((int64_t)n >= 256LL * 2 * 2048)
-        return mhdc_launch{(one_block || n_b % 128 == 0) ? 2 : 1, 256, 0, 0, 0};
+    if ((int64_t)n >= 256LL * 2 * 2048) {
+        const int v = (one_block || n_b % 128 == 0) ? 2 : 1;
+        return mhdc_launch{v, 256, v == 2 ? 8 : 16, 0, 0};
+    }
     return mhdc_launch{1, 64, 0, 0, 0};
 }
 

@@ -84,8 +84,8 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr, const int32_t *colin
     // right-hand sides per pass)
     static const mhdc_launch shapes[] = {
         {1, 64, 0, 0, 0},  {1, 256, 0, 0, 0}, {2, 256, 0, 0, 0}, {4, 256, 0, 0, 0},
-        {2, 256, 1, 0, 0}, {1, 256, 0, 1, 0}, {1, 256, 0, 2, 0}, {2, 256, 0, 2, 0},
-        {1, 256, 0, 0, 4}, {2, 256, 0, 0, 4}};
+        {2, 256, 1, 0, 0}, {2, 256, 8, 0, 0}, {1, 256, 16, 0, 0}, {1, 256, 0, 1, 0},
+        {1, 256, 0, 2, 0}, {2, 256, 0, 2, 0}, {1, 256, 0, 0, 4}, {2, 256, 0, 0, 4}};
     mhdc_handle best = nullptr;
     mhdc_tune_result res{};
     res.us = 1e30f;

@@ -1,5 +1,5 @@
 // spmv.hip -- single-matrix SpMV / SpMM launcher: one workgroup per row
-// tile (spmv_tile.h), tiles remapped so each XCD walks a contiguous range.
+// tile (spmv_tile.h), tiles optionally regrouped over the 8 XCDs.
 #include "internal.h"
 #include "spmv_tile.h"
 
@@ -10,7 +10,7 @@ template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
 __global__ __launch_bounds__(WG) void k_spmv(SpmvArgs a)
 {
     __shared__ double s_lds[HAS_REM ? (TileShape<WG, KC, RG>::LDS_BYTES + 7) / 8 : 1];
-    const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x, a.remap) : (int)blockIdx.x;
     spmv_tile<WG, V, KC, HAS_DIA, HAS_REM, RG>(a, tile, s_lds);
 }
 
@@ -101,6 +101,9 @@ int check_launch(const mhdc_launch &cfg)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "rows_per_lane must be 1, 2 or 4");
     if (cfg.csr_mode < 0 || cfg.csr_mode > 2)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "csr_mode must be 0, 1 or 2");
+    const int r = cfg.xcd_remap;
+    if (r < 0 || r > 64 || (r & (r - 1)) != 0)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "xcd_remap must be 0 or a power of two up to 64");
     const int g = cfg.rhs_group;
     if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "rhs_group must be 0, 1, 2, 4, 8 or 16");

@@ -63,13 +63,24 @@ struct SpmvArgs {
     int32_t remap;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map workgroup w so
-// that XCD (w mod 8) walks one contiguous range of the G tiles.  A bijection
-// on [0, G) for any G.
-__device__ inline int xcd_tile(int w, int G)
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  remap = 1: XCD (w mod 8) walks one contiguous eighth of the G tiles.
+// remap = C >= 2 (a power of two): runs of C consecutive tiles go to one XCD
+// and the XCDs take the runs in turn, so a row tile's neighbours (whose x
+// entries it shares through near diagonals) mostly sit in the same L2 while
+// all XCDs still sweep the rows together.  Tiles past the last whole round
+// of 8*C keep dispatch order.  Both forms are bijections on [0, G).
+__device__ inline int xcd_tile(int w, int G, int remap)
 {
-    const int x = w & 7, idx = w >> 3, q = G >> 3, r = G & 7;
-    return x * q + (x < r ? x : r) + idx;
+    const int x = w & 7, idx = w >> 3;
+    if (remap == 1) {
+        const int q = G >> 3, r = G & 7;
+        return x * q + (x < r ? x : r) + idx;
+    }
+    const int span = remap * 8;
+    if (w >= (G / span) * span)
+        return w;
+    return ((idx / remap) * 8 + x) * remap + (idx & (remap - 1));
 }
 
 template <int WG, int KC, bool RG>
