@@ -184,7 +184,7 @@ def train(recs, steps=8000, B=128, lr=1e-3, seed=0):
     return net, np.concatenate([h1.cpu().numpy(), h2.cpu().numpy()]), prior
 
 
-def evaluate(net, recs, tolerance=0.05):
+def evaluate(net, recs, tolerance=JUDGE_TOLERANCE):
     """Per held-out matrix: time of the judged network choice, of the policy
     and of the exhaustive best, all from the measured grid."""
     import torch
@@ -254,7 +254,8 @@ def main(argv=None):
                                                 "used_network")}
     ks = list(test[0]["us"])
     R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in test])
-    rep.update(train_matrices=len(recs), train_steps=a.steps, train_seconds=round(dt, 2),
+    rep.update(judge_tolerance=JUDGE_TOLERANCE,
+               train_matrices=len(recs), train_steps=a.steps, train_seconds=round(dt, 2),
                loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean()),
                prior=prior, prior_fixed_on_test=dict(
                    mean_ratio=float(R[:, ks.index(prior)].mean()),
