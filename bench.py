@@ -191,6 +191,22 @@ def main():
                       "us_per_step": round(t_hdc * 1e6, 2), "K": inf_h["K"]}
         out["speedup_vs_csr"] = round(t_csr / t_mhdc, 4)
         out["speedup_vs_csr_model"] = round(inf["rp_est"], 4)
+        # block size sweep on the same matrix (default launch of each handle)
+        sweep = {str(args.n_b): {"us": round(t_mhdc * 1e6, 2),
+                                 "gb_per_s": round(inf["bytes_alg"] / t_mhdc / 1e9, 1),
+                                 "K": inf["K"], "launch": launch}}
+        for nb in (128, 512, 1024, 2048, 4096):
+            if str(nb) in sweep:
+                continue
+            hs, _, ts, _, i_s = run_format(
+                lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, nb, args.theta), x,
+                max(args.steps // 4, 1), args.warmup, stream, "n_b=%d" % nb)
+            hs.close()
+            sweep[str(nb)] = {"us": round(ts * 1e6, 2),
+                              "gb_per_s": round(i_s["bytes_alg"] / ts / 1e9, 1), "K": i_s["K"],
+                              "launch": [i_s[f] for f in ("rows_per_lane", "wg_size", "xcd_remap",
+                                                          "csr_mode", "rhs_group")]}
+        out["n_b_sweep"] = dict(sorted(sweep.items(), key=lambda kv: int(kv[0])))
 
     # memory benchmark (Sec. 6.2, direct kernel): achievable HBM rate
     Ns = 1 << 27

@@ -29,10 +29,17 @@ struct BatchItem {
     int32_t rg;          // CSR part: stage values/columns (1) or products (0)
 };
 
+#ifndef BATCH_RG_FOR_MANY
+#define BATCH_RG_FOR_MANY 1
+#endif
+
+// LDS bytes of the CSR-part variants batch_tile() can run at this width.
 template <int WG, int KC>
 constexpr int lds_of()
 {
-    return std::max(TileShape<WG, KC, false>::LDS_BYTES, TileShape<WG, KC, true>::LDS_BYTES);
+    return (BATCH_RG_FOR_MANY && KC > 1)
+               ? TileShape<WG, KC, true>::LDS_BYTES
+               : std::max(TileShape<WG, KC, false>::LDS_BYTES, TileShape<WG, KC, true>::LDS_BYTES);
 }
 
 // Right-hand sides per pass over a tile in the persistent kernel (larger
@@ -40,9 +47,6 @@ constexpr int lds_of()
 // passes of 4 despite the larger register budget: every further pass reads
 // the tile's share of A again.
 constexpr int BATCH_MAX_KC = 16;
-#ifndef BATCH_RG_FOR_MANY
-#define BATCH_RG_FOR_MANY 1
-#endif
 
 template <int WG>
 constexpr int batch_lds_doubles()
@@ -61,16 +65,23 @@ constexpr int batch_lds_doubles()
 template <int WG, int KC>
 __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *lds)
 {
-    if (BATCH_RG_FOR_MANY && (KC > 1 || it.rg))
+    if constexpr (BATCH_RG_FOR_MANY && KC > 1) {
         spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);
-    else
-        spmv_tile<WG, 1, KC, true, true, false>(it.a, local, lds);
+    } else {
+        if (it.rg)
+            spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);
+        else
+            spmv_tile<WG, 1, KC, true, true, false>(it.a, local, lds);
+    }
 }
 
 __global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
 
+// Four waves per SIMD: the register cap (128) that the LDS footprint of a
+// 256-lane workgroup allows anyway; without it the compiler took 132 and
+// the machine held three workgroups per CU.
 template <int WG>
-__global__ __launch_bounds__(WG) void k_batch(const BatchItem *__restrict__ items, int32_t count,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(const BatchItem *__restrict__ items, int32_t count,
                                               int64_t total_tiles, int32_t *counter)
 {
     __shared__ double s_prod[batch_lds_doubles<WG>()];
