@@ -319,8 +319,20 @@ def test_model_eq28_matches_volumes():
 
 
 def test_stream_kernels():
+    """Sec. 6.2 kernels on integer-valued arrays, where every result is
+    exact: C[i] = 1 + i * (3 + i) for the direct kernel; the indirect kernel
+    with the reversed index reads B[n-1-i]; with the identity index it
+    equals the direct kernel; an index outside [0, n) leaves C[i] as is."""
+    n = 100
+    i = np.arange(n, dtype=np.float64)
+    A, B, C = i.copy(), 3.0 + i, np.ones(n)
+    assert np.array_equal(oracle.stream_direct(A, B, C), 1.0 + i * (3.0 + i))
+    rev = np.arange(n - 1, -1, -1, dtype=np.int32)
+    assert np.array_equal(oracle.stream_indirect(A, B, rev, C), 1.0 + i * (3.0 + (n - 1 - i)))
     rng = np.random.default_rng(0)
-    A, B, C = rng.random(100), rng.random(100), rng.random(100)
-    assert np.array_equal(oracle.stream_direct(A, B, C), C + A * B)
-    I = np.arange(100, dtype=np.int32)
-    assert np.array_equal(oracle.stream_indirect(A, B, I, C), C + A * B)
+    A, B, C = rng.random(n), rng.random(n), rng.random(n)
+    I = np.arange(n, dtype=np.int32)
+    assert np.array_equal(oracle.stream_indirect(A, B, I, C), oracle.stream_direct(A, B, C))
+    I[[3, 50]] = [-1, n]
+    got = oracle.stream_indirect(A, B, I, C)
+    assert got[3] == C[3] and got[50] == C[50]
