@@ -18,20 +18,17 @@ std::atomic<int32_t> g_fail_countdown{0};
 
 mhdc_launch default_launch(int32_t n, int32_t n_b)
 {
-    // Large matrices: 256-lane workgroups, 2 rows per lane when a wavefront's
-    // 128 rows stay inside one block (n_b a multiple of 128, or one block),
-    // else 1 so that n_b = 64, 192, ... keep the wave-uniform diagonal path.
+    // Large matrices: 256-lane workgroups, one row per lane, runs of 16 tiles
+    // (4096 rows) per XCD: a tile's neighbours, whose x entries it also reads
+    // through the near diagonals, then share its L2.  Measured on the 256^3
+    // heptadiagonal and the 192^3 partially diagonal cases, this shape is
+    // within 4% of the best of 7 shapes for every n_b tried and up to 8%
+    // faster than two rows per lane in dispatch order; one contiguous
+    // eighth per XCD (xcd_remap = 1) is 5% slower.
     // Small matrices: 64-lane workgroups so that the 256 CUs get work.
-    // Runs of 4096 consecutive rows per XCD (xcd_remap 8 or 16 tiles): a
-    // tile's neighbours, whose x entries it also reads through the near
-    // diagonals, then share its L2.  On the 256^3 heptadiagonal case this
-    // measured 2-4% faster than dispatch order; one contiguous eighth per
-    // XCD (xcd_remap = 1) measured 5% slower.
-    const bool one_block = n_b >= n;
-    if ((int64_t)n >= 256LL * 2 * 2048) {
-        const int v = (one_block || n_b % 128 == 0) ? 2 : 1;
-        return mhdc_launch{v, 256, v == 2 ? 8 : 16, 0, 0};
-    }
+    (void)n_b;
+    if ((int64_t)n >= 256LL * 2 * 2048)
+        return mhdc_launch{1, 256, 16, 0, 0};
     return mhdc_launch{1, 64, 0, 0, 0};
 }
 
@@ -57,7 +54,9 @@ void fill_info(const BdcMatrix &m, mhdc_info *o)
         o->bytes_paper = 12.0 * nnz + 4.0 * n + 16.0 * n;
     } else {
         o->bytes_alg = 8.0 * S + 4.0 * K + 4.0 * ((double)m.n_blk + 1) + 12.0 * R +
-                       (m.R > 0 ? 4.0 * (n + 1) : 0.0) + 16.0 * n;
+                       (m.R > 0 ? 4.0 * (n + 1) : 0.0) +
+                       (m.rem_mask ? 4.0 * (double)rem_mask_words(m.n) : 0.0) +
+                       16.0 * n;
         o->bytes_paper = 12.0 * R + 4.0 * n + 8.0 * S + 16.0 * n;
     }
     const double v_csr = 12.0 * nnz + 4.0 * n + 16.0 * n;

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         int32_t lo = 0, hi = count - 1;
         while (lo < hi) {
             const int32_t mid = (lo + hi + 1) >> 1;
-            if (items[mid].tile_begin <= t)
+            if (uniform_load(&items[mid].tile_begin, 0) <= t)
                 lo = mid;
             else
                 hi = mid - 1;
@@ -183,7 +183,9 @@ int upload_items(mhdc_batch_s *b, const double *const *X, const int64_t *ldx, do
             a_bytes = 12.0 * (double)m.nnz + 4.0 * (n + 1);
         else
             a_bytes = 8.0 * (double)m.S + 4.0 * (double)m.K + 4.0 * ((double)m.n_blk + 1) +
-                      12.0 * (double)m.R + (m.R > 0 ? 4.0 * (n + 1) : 0.0);
+                      12.0 * (double)m.R +
+                      (m.R > 0 ? 4.0 * (n + 1) : 0.0) +
+                      (m.rem_mask ? 4.0 * (double)rem_mask_words(m.n) : 0.0);
         bytes += a_bytes + 16.0 * n * k;
     }
     if (tiles > INT32_MAX)

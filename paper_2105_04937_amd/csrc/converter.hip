@@ -252,6 +252,27 @@ __global__ __launch_bounds__(CV_WG) void k_scatter_rem(int32_t n, int32_t n_b,
     }
 }
 
+// One lane per 32-bit word of the remainder mask: bit b of word w is set
+// when rows [64(32w+b), 64(32w+b)+64) hold remainder entries.
+__global__ __launch_bounds__(CV_WG) void k_rem_mask(int32_t n, int64_t words,
+                                                    const int32_t *__restrict__ rem_ptr,
+                                                    uint32_t *__restrict__ mask)
+{
+    for (int64_t w = (int64_t)blockIdx.x * CV_WG + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * CV_WG) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; b++) {
+            const int64_t r0 = (w * 32 + b) * 64;
+            if (r0 >= n)
+                break;
+            const int64_t r1 = r0 + 64 < n ? r0 + 64 : n;
+            if (rem_ptr[r1] > rem_ptr[r0])
+                bits |= 1u << b;
+        }
+        mask[w] = bits;
+    }
+}
+
 // ---------------------------------------------------------------- decode
 __global__ __launch_bounds__(CV_WG) void k_decode_count(int32_t n, int32_t n_b,
                                                         const int32_t *__restrict__ dia_ptr,
@@ -399,8 +420,10 @@ void free_matrix(BdcMatrix &m)
     dfree(m.rem_ptr);
     dfree(m.rem_col);
     dfree(m.rem_val);
+    dfree(m.rem_mask);
     m.dia_ptr = m.dia_off = m.rem_ptr = m.rem_col = nullptr;
     m.dia_val = m.rem_val = nullptr;
+    m.rem_mask = nullptr;
 }
 
 int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const double *val)
@@ -563,6 +586,25 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
             return rc;
         k_scatter_rem<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(
             n, n_b, rowptr, colind, val, m.dia_ptr, m.dia_off, m.rem_ptr, m.rem_col, m.rem_val);
+        const int64_t words = rem_mask_words(n);
+        if ((rc = dmalloc((void **)&m.rem_mask, sizeof(uint32_t) * (size_t)words, "rem_mask")))
+            return rc;
+        k_rem_mask<<<grid_for(words, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, words, m.rem_ptr,
+                                                                     m.rem_mask);
+        if ((rc = launch_ok("remainder mask")))
+            return rc;
+        // Keep the mask only where most row groups have no remainder: where
+        // most have one, testing it first would only add a round trip.
+        std::vector<uint32_t> h((size_t)words);
+        MHDC_HIP_CHECK(hipMemcpy(h.data(), m.rem_mask, sizeof(uint32_t) * (size_t)words,
+                                 hipMemcpyDeviceToHost));
+        int64_t set = 0;
+        for (uint32_t w : h)
+            set += __builtin_popcount(w);
+        if (2 * set > ((int64_t)n + 63) / 64) {
+            dfree(m.rem_mask);
+            m.rem_mask = nullptr;
+        }
     }
     return sync_ok("conversion");
 }

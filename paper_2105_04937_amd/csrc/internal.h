@@ -29,9 +29,17 @@ struct BdcMatrix {
     int32_t *rem_ptr = nullptr;  // [n+1]
     int32_t *rem_col = nullptr;  // [R]
     double *rem_val = nullptr;   // [R]
+    // Blocked kinds with R > 0: bit g of word g/32 is set when rows
+    // [64g, 64g+64) hold remainder entries (ceil(n/2048) words).  A tile
+    // tests its bits in this small, cache-resident array instead of
+    // fetching rem_ptr from HBM before it can start on its diagonals.
+    uint32_t *rem_mask = nullptr;
     int device = 0;
     mhdc_launch launch{2, 256, 0, 0, 0};
 };
+
+// Words of BdcMatrix::rem_mask for n rows (one bit per 64 rows).
+inline int64_t rem_mask_words(int64_t n) { return (n + 2047) / 2048; }
 
 // Thread-local error state.
 int set_error(int code, const std::string &msg);

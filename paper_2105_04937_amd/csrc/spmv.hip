@@ -120,6 +120,7 @@ SpmvArgs make_args(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
     a.dia_off = m.dia_off;
     a.dia_val = m.dia_val;
     a.rem_ptr = m.rem_ptr;
+    a.rem_mask = m.rem_mask;
     a.rem_col = m.rem_col;
     a.rem_val = m.rem_val;
     a.X = X;

@@ -61,6 +61,7 @@ struct SpmvArgs {
     int32_t has_rem;
     int32_t uniform;
     int32_t remap;
+    const uint32_t *rem_mask;  // one bit per 64 rows, or null: test rem_ptr
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -81,6 +82,29 @@ __device__ inline int xcd_tile(int w, int G, int remap)
     if (w >= (G / span) * span)
         return w;
     return ((idx / remap) * 8 + x) * remap + (idx & (remap - 1));
+}
+
+// Wave-uniform read of data no kernel writes while it runs (block and
+// remainder pointers, offsets, the remainder mask, batch descriptors),
+// through the constant address space so that it becomes a scalar load even
+// after a workgroup barrier (after which the compiler can no longer prove on
+// its own that global memory is unchanged, and falls back to one vector
+// load and wait per value).
+template <typename E>
+__device__ inline E uniform_load(const E *p, int64_t i)
+{
+    using const_e = const __attribute__((address_space(4))) E;
+    return ((const_e *)p)[i];
+}
+
+// Format metadata read through uniform_load (SCALAR) or as plain loads.
+template <bool SCALAR, typename E>
+__device__ inline E meta_load(const E *p, int64_t i)
+{
+    if constexpr (SCALAR)
+        return uniform_load(p, i);
+    else
+        return p[i];
 }
 
 template <int WG, int KC, bool RG>
@@ -123,10 +147,33 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
         for (int r = 0; r < KC; r++)
             acc[v][r] = 0.0;
 
-    if (HAS_REM && a.has_rem) {
+    // Scalar metadata loads up to 4 columns; at 8 and 16 the scalar
+    // registers are taken by the column addresses.
+    constexpr bool SM = KC <= 4;
+    // Wave-uniform DIA range, loaded before the remainder pointers are
+    // looked at so that the two scalar loads share one memory round trip
+    // (most tiles of a mostly-diagonal matrix have no remainder entries).
+    const bool dia_uniform = HAS_DIA && a.has_dia && a.uniform && wave_base < n;
+    int64_t u_ib = 0;
+    int32_t u_kb0 = 0, u_kb1 = 0;
+    if (SM && dia_uniform) {
+        u_ib = wave_base / a.n_b;
+        u_kb0 = uniform_load(a.dia_ptr, u_ib);
+        u_kb1 = uniform_load(a.dia_ptr, u_ib + 1);
+    }
+
+    // A tile covers T/64 whole groups of 64 rows inside one mask word.
+    static_assert(T % 64 == 0 && 32 % (T / 64) == 0, "tile must cover 64-row groups of one word");
+    bool tile_rem = HAS_REM && a.has_rem;
+    if (tile_rem && a.rem_mask) {
+        const int64_t g0 = tile_base >> 6;
+        const uint32_t word = meta_load<SM>(a.rem_mask, g0 >> 5);
+        tile_rem = ((word >> (g0 & 31)) & (T == 2048 ? 0xffffffffu : ((1u << (T / 64)) - 1u))) != 0;
+    }
+    if (tile_rem) {
         const int64_t tile_end = tile_base + T < n ? tile_base + T : n;
-        const int32_t e_beg = a.rem_ptr[tile_base];
-        const int32_t e_end = a.rem_ptr[tile_end];
+        const int32_t e_beg = meta_load<SM>(a.rem_ptr, tile_base);
+        const int32_t e_end = meta_load<SM>(a.rem_ptr, tile_end);
         if (e_beg < e_end) {
             int32_t rs[V], re[V];
 #pragma unroll
@@ -202,18 +249,26 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
     }
 
     if (HAS_DIA && a.has_dia && wave_base < n) {
-        if (a.uniform) {
-            // All rows of this wavefront lie in block ib.
-            const int64_t ib = wave_base / a.n_b;
-            const int64_t t0 = wave_base - ib * a.n_b;
-            const int32_t kb0 = a.dia_ptr[ib], kb1 = a.dia_ptr[ib + 1];
-            for (int32_t kk = kb0; kk < kb1; kk += U) {
+        // (a.uniform where the range is loaded here: the compiler's register
+        // allocation of the 8- and 16-column kernels is much worse with the
+        // hoisted flag)
+        if (SM ? dia_uniform : a.uniform != 0) {
+            // All rows of this wavefront lie in block u_ib.
+            if (!SM) {
+                u_ib = wave_base / a.n_b;
+                u_kb0 = a.dia_ptr[u_ib];
+                u_kb1 = a.dia_ptr[u_ib + 1];
+            }
+            const int64_t t0 = wave_base - u_ib * a.n_b;
+            const int32_t kb1 = u_kb1;
+            for (int32_t kk = u_kb0; kk < kb1; kk += U) {
                 int64_t off[U];
                 bool live[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     live[u] = kk + u < kb1;
-                    off[u] = live[u] ? a.dia_off[kk + u] : 0;
+                    // clamped index: unconditional loads that issue together
+                    off[u] = meta_load<SM>(a.dia_off, live[u] ? kk + u : kb1 - 1);
                 }
                 double w[U][V], xv[U][V][KC];
                 bool in[U][V];
