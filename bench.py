@@ -97,6 +97,7 @@ def cpu_baseline(m, x, nnz):
     """The oracle's CSR SpMV (plain C, FP64, one OpenMP thread per host core)
     on the same matrix, with the paper's protocol (best over n_loops = 5 of
     the mean over n_ites = 20 calls); plus one single-thread loop."""
+    os.environ.setdefault("OMP_PROC_BIND", "close")  # the paper's compact placement
     import oracle
     cores = len(os.sched_getaffinity(0))
     oracle.csr_spmv(m.rowptr, m.colind, m.val, x, cores)  # warm-up
@@ -147,6 +148,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-partial", action="store_true")
     ap.add_argument("--only-mhdc", action="store_true", help="time the M-HDC kernel only")
+    ap.add_argument("--pp-ites", type=int, default=1000,
+                    help="paper protocol: calls per loop (n_ites of Fig. 18)")
+    ap.add_argument("--pp-loops", type=int, default=20,
+                    help="paper protocol: loops, best taken (n_loops of Fig. 18)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -172,7 +177,7 @@ def main():
     h, y, t_mhdc, conv_mhdc, inf = run_format(
         lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, args.n_b, args.theta), x, args.steps,
         args.warmup, stream, "M-HDC")
-    t_pp = paper_protocol(lambda: h.spmv(x, y, stream), 100, 5, stream)
+    t_pp = paper_protocol(lambda: h.spmv(x, y, stream), args.pp_ites, args.pp_loops, stream)
     launch = [inf[f] for f in ("rows_per_lane", "wg_size", "xcd_remap", "csr_mode", "rhs_group")]
     out = {}
     if not args.only_mhdc:
@@ -258,6 +263,7 @@ def main():
 
     gflops = 2.0 * inf["nnz"] / t_mhdc / 1e9
     achieved = inf["bytes_alg"] / t_mhdc / 1e9
+    traffic = kernel_traffic(launch)
     rec = {
         "metric": "M-HDC SpMV GFLOP/s + HBM GB/s vs GPU CSR, FP64, 1xMI355X",
         "value": round(gflops, 2),
@@ -278,10 +284,14 @@ def main():
         "hbm_gb_per_s": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": kernel_traffic(launch)},
+                     "traffic": traffic},
         "bytes_alg_per_launch": inf["bytes_alg"],
         "bytes_paper_model": inf["bytes_paper"],
+        # counted HBM bytes against the algorithmic bytes and the paper's V
+        "traffic_vs_alg": round(traffic / inf["bytes_alg"], 4) if traffic else None,
+        "traffic_vs_paper_model": round(traffic / inf["bytes_paper"], 4) if traffic else None,
         "paper_protocol_us": round(t_pp * 1e6, 2),
+        "paper_protocol": {"n_ites": args.pp_ites, "n_loops": args.pp_loops},
         "convert_s": round(conv_mhdc, 3),
         "stream_direct_gb_per_s": round(stream_gbs, 1),
         "cpu_baseline": cpu,
