@@ -429,5 +429,6 @@ void orc_stream_indirect(int64_t N, const double *A, const double *B,
                          const int32_t *I, double *C)
 {
     for (int64_t i = 0; i < N; i++)
-        C[i] += A[i] * B[I[i]];
+        if (I[i] >= 0 && I[i] < N)  /* an index outside [0, N) leaves C[i] */
+            C[i] += A[i] * B[I[i]];
 }

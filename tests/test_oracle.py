@@ -336,3 +336,28 @@ def test_stream_kernels():
     I[[3, 50]] = [-1, n]
     got = oracle.stream_indirect(A, B, I, C)
     assert got[3] == C[3] and got[50] == C[50]
+
+
+@pytest.mark.parametrize("n,points", [(1000, 3), (1024, 5), (1000, 7), (999, 7)])
+def test_banded_stencil_dia_closed_forms(n, points):
+    """Sec. 6.3 banded stencils are pure DIA: HDC at theta = 0 keeps exactly
+    the band offsets with an empty remainder and S = n per diagonal; with
+    integer values every product and sum is exact, so the HDC kernel (Fig. 8)
+    equals the CSR definition bit for bit; the per-block selection of M-HDC
+    at theta = 1 keeps an offset in a block iff all its rows have it."""
+    from paper_2105_04937_amd import synth
+    m = synth.banded_stencil(n, points, 3)
+    offs = synth.banded_offsets(n, points)
+    h = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.0)
+    assert list(h.dia_off) == offs and h.R == 0 and h.dia_val.size == len(offs) * n
+    vi = np.round(m.val * 4.0)  # small integers: exact arithmetic
+    vi[vi == 0] = 1.0
+    x = np.arange(n, dtype=np.float64) % 7 - 3
+    hi = oracle.hdc_from_csr(m.rowptr, m.colind, vi, 0.0)
+    assert np.array_equal(oracle.hdc_spmv(hi, x), oracle.csr_spmv(m.rowptr, m.colind, vi, x))
+    bl = 64
+    mb = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, 1.0)
+    for ib in range(mb.n_blk):
+        r0, r1 = ib * bl, min(n, ib * bl + bl)
+        want = [o for o in offs if all(0 <= i + o < n for i in range(r0, r1))]
+        assert list(mb.dia_off[mb.dia_ptr[ib]:mb.dia_ptr[ib + 1]]) == want
