@@ -168,6 +168,14 @@ hdc_handle hdc_from_csr(int32_t n, const int32_t *rowptr,
                         const int32_t *colind, const double *val,
                         double threshold);
 int hdc_spmv(hdc_handle h, const double *x, double *y, hipStream_t stream);
+/* The HDC kernel without cache blocking (Fig. 8; Fig. 5's DIA kernel when
+ * the CSR part is empty): y is set to the CSR part's product, then every
+ * diagonal is added in a pass of its own over y, in ascending offset order
+ * (Sec. 4.1: y and x move once per diagonal).  Same bits as hdc_spmv; kept
+ * as the baseline of the paper's stencil study (Sec. 6.3).  x and y hold
+ * n doubles and must not overlap.  Asynchronous: 1 + K launches. */
+int hdc_spmv_unblocked(hdc_handle h, const double *x, double *y,
+                       hipStream_t stream);
 int hdc_spmm(hdc_handle h, const double *X, int64_t ldx, double *Y,
              int64_t ldy, int32_t k, hipStream_t stream);
 int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val,

@@ -16,19 +16,26 @@ thread_local std::string t_msg;
 std::atomic<int32_t> g_fail_countdown{0};
 }  // namespace
 
-mhdc_launch default_launch(int32_t n, int32_t n_b)
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz)
 {
-    // Large matrices: 256-lane workgroups, one row per lane, runs of 16 tiles
-    // (4096 rows) per XCD: a tile's neighbours, whose x entries it also reads
-    // through the near diagonals, then share its L2.  Measured on the 256^3
-    // heptadiagonal and the 192^3 partially diagonal cases, this shape is
-    // within 4% of the best of 7 shapes for every n_b tried and up to 8%
-    // faster than two rows per lane in dispatch order; one contiguous
-    // eighth per XCD (xcd_remap = 1) is 5% slower.
+    // Large matrices: 256-lane workgroups, runs of 4096 consecutive rows per
+    // XCD: a tile's neighbours, whose x entries it also reads through the
+    // near diagonals, then share its L2 (one contiguous eighth per XCD,
+    // xcd_remap = 1, is 5% slower).  One row per lane, or two where rows are
+    // short (under 4 stored entries on average: a 256-row tile of the banded
+    // 3-point matrix moves too little per workgroup and runs 33% slower than
+    // a 512-row one); two rows per lane keep the wave-uniform diagonal path
+    // only when n_b is a multiple of 128 (or the matrix one block).  On the
+    // 256^3 heptadiagonal and the 192^3 partially diagonal cases the default
+    // is within 4% of the best of 7 shapes for every n_b tried.
     // Small matrices: 64-lane workgroups so that the 256 CUs get work.
-    (void)n_b;
-    if ((int64_t)n >= 256LL * 2 * 2048)
+    if ((int64_t)n >= 256LL * 2 * 2048) {
+        const bool short_rows = nnz > 0 && nnz < 4LL * n;
+        const bool v2_uniform = n_b <= 0 || n_b >= n || n_b % 128 == 0;
+        if (short_rows && v2_uniform)
+            return mhdc_launch{2, 256, 8, 0, 0};
         return mhdc_launch{1, 256, 16, 0, 0};
+    }
     return mhdc_launch{1, 64, 0, 0, 0};
 }
 
@@ -91,7 +98,7 @@ H *make_handle(int kind, int32_t n, int32_t n_b, double theta)
     h->m.n = n;
     h->m.n_b = n_b;
     h->m.theta = theta;
-    h->m.launch = default_launch(n, n_b);
+    h->m.launch = default_launch(n, n_b, 0);
     (void)hipGetDevice(&h->m.device);
     return h;
 }
@@ -104,6 +111,7 @@ H *finish(H *h, int rc)
         delete h;
         return nullptr;
     }
+    h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz);
     return h;
 }
 

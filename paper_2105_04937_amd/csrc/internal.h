@@ -77,6 +77,9 @@ int kc_for(int k);
 bool row_gather(int32_t csr_mode, int kc);
 int check_operands(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
                    int64_t ldy, int32_t k);
+// y = the CSR part's product alone (zero rows where the part is empty), one
+// right-hand side: the first pass of the unblocked HDC kernel.
+int launch_rem_part(const BdcMatrix &m, const double *x, double *y, hipStream_t stream);
 int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y,
                 int64_t ldy, int32_t k, hipStream_t stream);
 int check_launch(const mhdc_launch &cfg);
@@ -87,7 +90,7 @@ int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
                        int64_t *total, hipStream_t stream);
 
 // api.hip: handle creation shared with the autotuner
-mhdc_launch default_launch(int32_t n, int32_t n_b);
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz);
 
 }  // namespace mhdc
 

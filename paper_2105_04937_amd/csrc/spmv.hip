@@ -194,4 +194,30 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
     return MHDC_OK;
 }
 
+int launch_rem_part(const BdcMatrix &m, const double *x, double *y, hipStream_t stream)
+{
+    int rc = check_operands(m, x, m.n, y, m.n, 1);
+    if (rc || m.n == 0)
+        return rc;
+    if (m.R == 0) {
+        const int64_t g = ((int64_t)m.n + 255) / 256;
+        k_zero_cols<<<dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, stream>>>(y, m.n,
+                                                                                      m.n, 1);
+    } else {
+        const int32_t v = m.launch.rows_per_lane, wg = m.launch.wg_size;
+        KernelFn fn = pick(wg, v, 1, 2 | (row_gather(m.launch.csr_mode, 1) ? 4 : 0));
+        if (!fn)
+            return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
+        SpmvArgs a = make_args(m, x, m.n, y, m.n, 1, v);
+        a.has_dia = 0;
+        const int64_t T = (int64_t)wg * v;
+        const int64_t tiles = ((int64_t)m.n + T - 1) / T;
+        hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(wg), 0, stream, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string("remainder launch: ") + hipGetErrorString(e));
+    return MHDC_OK;
+}
+
 }  // namespace mhdc

@@ -96,6 +96,7 @@ SIGNATURES = {
     "mhdc_destroy": (None, [_vp]),
     "hdc_from_csr": (_vp, [_i32, _vp, _vp, _vp, _f64]),
     "hdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "hdc_spmv_unblocked": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "hdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "hdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
@@ -313,6 +314,17 @@ class HDCMatrix(_Matrix):
         if not h:
             _raise()
         return cls(h, n)
+
+    def spmv_unblocked(self, x, y=None, stream=None):
+        """y = A x with the unblocked HDC kernel (Fig. 8): the CSR part, then
+        one pass over y per diagonal.  Same bits as spmv()."""
+        if x.numel() != self.n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), self.n))
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        _check(lib().hdc_spmv_unblocked(self._h, _dptr(x, torch.float64, "x"),
+                                        _dptr(y, torch.float64, "y"), _stream(stream)))
+        return y
 
     def export(self):
         inf = self.info()

@@ -276,6 +276,80 @@ def stencil_matrix_gpu(N: int, seed: int, points: int = 27, drop=0.0, extra_per_
     return rowptr.to(torch.int32), colind.to(torch.int32), val
 
 
+def banded_offsets(n: int, points: int):
+    """Offsets of the paper's banded stencil matrices (Sec. 6.3): 3 points
+    {0, +-1}; 5 points adds +-n_x with n_x = floor(sqrt(n)); 7 points adds
+    +-n_x and +-n_x^2 with n_x = floor(cbrt(n)).  Ascending."""
+    if points == 3:
+        offs = [0, 1]
+    elif points == 5:
+        nx = int(np.floor(np.sqrt(n)))
+        while (nx + 1) * (nx + 1) <= n:
+            nx += 1
+        while nx * nx > n:
+            nx -= 1
+        offs = [0, 1, nx]
+    elif points == 7:
+        nx = int(round(n ** (1.0 / 3.0)))
+        while (nx + 1) ** 3 <= n:
+            nx += 1
+        while nx ** 3 > n:
+            nx -= 1
+        offs = [0, 1, nx, nx * nx]
+    else:
+        raise ValueError("points must be 3, 5 or 7")
+    return sorted(set([-o for o in offs] + offs))
+
+
+def banded_stencil(n: int, points: int, seed: int) -> CSRMatrix:
+    """Banded stencil matrix of Sec. 6.3: a_ij != 0 exactly for j - i in
+    banded_offsets(n, points) and 0 <= j < n (no truncation at grid faces);
+    off-diagonals U[-1, -0.5] in CSR order, diagonal 1.01 * |row sum|."""
+    rng = np.random.default_rng(seed)
+    offs = np.asarray(banded_offsets(n, points), dtype=np.int64)
+    i = np.arange(n, dtype=np.int64)
+    cols = i[:, None] + offs[None, :]
+    keep = (cols >= 0) & (cols < n)
+    counts = keep.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(counts)
+    colind = cols[keep]
+    rows = np.repeat(i, counts)
+    val = rng.uniform(-1.0, -0.5, size=colind.size)
+    is_diag = colind == rows
+    val[is_diag] = 0.0
+    rs = np.zeros(n)
+    np.add.at(rs, rows, val)
+    val[is_diag] = 1.01 * np.abs(rs)
+    return CSRMatrix(n, rowptr.astype(np.int32), colind.astype(np.int32), val,
+                     dict(kind="banded", points=points, offsets=[int(o) for o in offs]))
+
+
+def banded_stencil_gpu(n: int, points: int, seed: int, device="cuda"):
+    """Device-side banded_stencil() (same structure and value rule, torch
+    generator, different random stream) for sizes up to 5e7 rows.  Returns
+    (rowptr, colind, val) device tensors (int32, int32, float64)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    offs = torch.as_tensor(banded_offsets(n, points), dtype=torch.int64, device=device)
+    i = torch.arange(n, dtype=torch.int64, device=device)
+    cols = i[:, None] + offs[None, :]
+    keep = (cols >= 0) & (cols < n)
+    counts = keep.sum(dim=1)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    colind = cols[keep]
+    del cols, keep
+    rows = torch.repeat_interleave(i, counts)
+    val = torch.rand(colind.numel(), generator=g, device=device, dtype=torch.float64) * 0.5 - 1.0
+    is_diag = colind == rows
+    val = torch.where(is_diag, torch.zeros_like(val), val)
+    rs = torch.zeros(n, dtype=torch.float64, device=device).index_add_(0, rows, val)
+    val = torch.where(is_diag, 1.01 * rs.abs()[rows], val)
+    return rowptr.to(torch.int32), colind.to(torch.int32), val
+
+
 def vector(n: int, seed: int, k: int = 1) -> np.ndarray:
     """x ~ U[-1, 1]; shape (n,) for k == 1, else (n, k) column-major."""
     rng = np.random.default_rng([seed, 1])

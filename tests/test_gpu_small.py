@@ -131,6 +131,34 @@ def test_launch_shapes_give_identical_bits():
         assert_same_bits(y, first, "csr shape %s" % (shp,))
 
 
+def test_hdc_unblocked_matches_blocked():
+    """The unblocked HDC kernel (Fig. 8; Fig. 5 for a pure DIA matrix) adds
+    the same rounded products in the same order per row as the blocked
+    kernel: bit-identical to hdc_spmv and to the oracle's Fig. 8 kernel, on
+    random matrices with a CSR part and on the banded stencils of Sec. 6.3
+    (with ragged sizes and n_x = 1)."""
+    cases = [(synth.random_csr(300, 5, density=0.05, bands=(-7, 0, 3), zero_frac=0.05), t)
+             for t in (0.0, 0.5, 0.9)]
+    cases += [(synth.banded_stencil(n, p, 2), 0.0) for n, p in
+              ((1, 3), (5, 5), (7, 7), (1000, 3), (4097, 5), (100_001, 7))]
+    cases.append((synth.partially_diagonal(14, 4, drop=0.3), 0.6))
+    for m, theta in cases:
+        say("case: unblocked HDC n=%d theta=%g" % (m.n, theta))
+        rp, ci, v = dev(m)
+        x = synth.vector(m.n, 9)
+        xd = torch.from_numpy(x).cuda()
+        h = mhdc.HDCMatrix.from_csr(rp, ci, v, theta)
+        want = oracle.hdc_spmv(oracle.hdc_from_csr(m.rowptr, m.colind, m.val, theta), x)
+        for shp in ((1, 64, 0), (2, 256, 1), (1, 256, 0, 2)):
+            h.set_launch(*shp)
+            yb = h.spmv(xd).cpu().numpy()
+            yu = h.spmv_unblocked(xd).cpu().numpy()
+            assert_same_bits(yu, yb, "unblocked vs blocked n=%d shape %s" % (m.n, shp))
+            assert_oracle_bits(yu, want, "unblocked vs oracle n=%d" % m.n)
+        h.close()
+    assert mhdc.lib().hdc_spmv_unblocked(None, None, None, None) == -1  # MHDC_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 11, 16])
 def test_multi_rhs(k):
     m = synth.partially_diagonal(14, 21, drop=0.2)

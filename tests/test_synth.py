@@ -1,5 +1,6 @@
 """Structure of the seeded synthetic inputs (no method arithmetic involved)."""
 import numpy as np
+import pytest
 
 from paper_2105_04937_amd import synth
 
@@ -66,3 +67,31 @@ def test_vector():
     assert x.shape == (1000,) and x.min() >= -1 and x.max() <= 1
     X = synth.vector(100, 1, k=4)
     assert X.shape == (100, 4) and X.flags.f_contiguous
+
+
+def test_banded_offsets():
+    """Sec. 6.3: n_x = floor(sqrt(n)) for 5 points, floor(cbrt(n)) for 7."""
+    assert synth.banded_offsets(100, 3) == [-1, 0, 1]
+    assert synth.banded_offsets(99, 5) == [-9, -1, 0, 1, 9]
+    assert synth.banded_offsets(100, 5) == [-10, -1, 0, 1, 10]
+    assert synth.banded_offsets(999, 7) == [-81, -9, -1, 0, 1, 9, 81]
+    assert synth.banded_offsets(1000, 7) == [-100, -10, -1, 0, 1, 10, 100]
+    assert synth.banded_offsets(50_000_000, 7)[-1] == 368 * 368
+    assert synth.banded_offsets(3, 5) == [-1, 0, 1]  # n_x = 1 merges with +-1
+
+
+@pytest.mark.parametrize("n,points", [(1, 3), (7, 7), (64, 5), (1000, 7), (1001, 3)])
+def test_banded_stencil_structure(n, points):
+    m = synth.banded_stencil(n, points, 5)
+    offs = synth.banded_offsets(n, points)
+    for i in range(n):
+        cols = m.colind[m.rowptr[i]:m.rowptr[i + 1]]
+        assert list(cols) == [i + o for o in offs if 0 <= i + o < n]
+        v = m.val[m.rowptr[i]:m.rowptr[i + 1]]
+        off = v[cols != i]
+        assert np.all((off >= -1.0) & (off < -0.5))
+        assert v[cols == i][0] == 1.01 * abs(off.sum())
+    # the device generator builds the same structure
+    import torch
+    rp, ci, _ = synth.banded_stencil_gpu(n, points, 5, device="cpu")
+    assert np.array_equal(rp.numpy(), m.rowptr) and np.array_equal(ci.numpy(), m.colind)
