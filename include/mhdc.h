@@ -110,7 +110,10 @@ typedef struct {
  * right-hand side and 2 for several; rhs_group in {0, 1, 2, 4, 8, 16}:
  * right-hand sides processed per pass over a tile (0 = all, up to 16; a
  * further pass reads the tile's share of A again from the caches).  Every
- * variant gives the same bits.  Set before use, not while spmv calls on the
+ * variant gives the same bits.  A new handle starts with {1, 256, 16, 0, 0}
+ * for n >= 2^20 rows ({2, 256, 8, 0, 0} when it averages under 4 stored
+ * entries per row and n_b is a multiple of 128 or the whole matrix) and
+ * {1, 64, 0, 0, 0} below.  Set before use, not while spmv calls on the
  * handle are in flight. */
 typedef struct {
     int32_t rows_per_lane;

@@ -29,17 +29,12 @@ struct BatchItem {
     int32_t rg;          // CSR part: stage values/columns (1) or products (0)
 };
 
-#ifndef BATCH_RG_FOR_MANY
-#define BATCH_RG_FOR_MANY 1
-#endif
-
 // LDS bytes of the CSR-part variants batch_tile() can run at this width.
 template <int WG, int KC>
 constexpr int lds_of()
 {
-    return (BATCH_RG_FOR_MANY && KC > 1)
-               ? TileShape<WG, KC, true>::LDS_BYTES
-               : std::max(TileShape<WG, KC, false>::LDS_BYTES, TileShape<WG, KC, true>::LDS_BYTES);
+    return KC > 1 ? TileShape<WG, KC, true>::LDS_BYTES
+                  : std::max(TileShape<WG, KC, false>::LDS_BYTES, TileShape<WG, KC, true>::LDS_BYTES);
 }
 
 // Right-hand sides per pass over a tile in the persistent kernel (larger
@@ -65,7 +60,7 @@ constexpr int batch_lds_doubles()
 template <int WG, int KC>
 __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *lds)
 {
-    if constexpr (BATCH_RG_FOR_MANY && KC > 1) {
+    if constexpr (KC > 1) {
         spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);
     } else {
         if (it.rg)
