@@ -133,3 +133,34 @@ def test_autotune(k):
     Y = h.spmm(torch.from_numpy(X).cuda()).cpu().numpy()
     for r in range(k):
         assert_oracle_bits(Y[r], oracle.mhdc_spmv(ref, X[r]), "autotuned rhs %d" % r)
+
+
+def test_full_batch_configuration():
+    """The benchmarked batch at its full size: 64 members (grid side
+    U{16..96}, 7/19/27 points, drop U[0, 0.3], k = U{1..16}; matrix i from
+    seed 4000 + i), n_b = 256, theta = 0.6.  One graph replay equals the 64
+    single launches bit for bit, and for every eighth member each column
+    equals the oracle's sequential M-HDC kernel (Fig. 16) bit for bit."""
+    say("case: full 64-member batch")
+    mats, Xs, members = [], [], []
+    for i in range(64):
+        m, k = synth.batch_member(i)
+        mats.append(mhdc.MHDCMatrix.from_csr(*dev(m), 256, 0.6))
+        X = np.random.default_rng([4000 + i, 2]).uniform(-1, 1, size=(k, m.n))
+        Xs.append(torch.from_numpy(np.ascontiguousarray(X)).cuda())
+        members.append((m, k))
+    b = mhdc.Batch(mats, Xs)
+    stream = torch.cuda.Stream()
+    b.graph_launch(stream)
+    stream.synchronize()
+    for j, ((m, k), mat, X, Y) in enumerate(zip(members, mats, Xs, b.Ys)):
+        single = mat.spmm(X)
+        assert_same_bits(Y.cpu().numpy(), single.cpu().numpy(), "member %d vs single" % j)
+        if j % 8 == 0:
+            ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6)
+            Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+            for r in range(k):
+                assert_oracle_bits(Yh[r], oracle.mhdc_spmv(ref, Xh[r]), "member %d rhs %d" % (j, r))
+    b.close()
+    for mat in mats:
+        mat.close()
