@@ -6,7 +6,8 @@ launch, so algorithmic bytes = A + 16 n k.  Each handle runs its default
 launch shape; a step is one spmm with inputs resident in HBM, timed with
 HIP events on the launch stream.
 
-    python bench_spmm.py [--steps K] [--warmup W]
+    python bench_spmm.py [--steps K] [--warmup W] [--matrix all|hepta|partial]
+                         [--ks 1,2,4,8,16] [--formats mhdc,csr]
 
 Prints one JSON line; value = GFLOP/s of M-HDC at k = 16 on the 256^3 case.
 """
@@ -43,7 +44,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--matrix", choices=("all", "hepta", "partial"), default="all")
+    ap.add_argument("--ks", default="1,2,4,8,16", help="right-hand side counts, comma-separated")
+    ap.add_argument("--formats", default="mhdc,csr", help="subset of mhdc,csr")
     args = ap.parse_args()
+    ks = [int(t) for t in args.ks.split(",")]
+    formats = args.formats.split(",")
 
     import torch
 
@@ -54,17 +60,22 @@ def main():
     rows = []
     cases = (("heptadiagonal 7-point 256^3", lambda: synth.heptadiagonal(256, 2), 256),
              ("partially diagonal 27-point 192^3", lambda: synth.partially_diagonal(192, 3), 128))
+    cases = [c for c in cases if args.matrix == "all" or c[0].startswith(
+        {"hepta": "heptadiagonal", "partial": "partially"}[args.matrix])]
     for name, gen, nb in cases:
         log("generating %s" % name)
         m = gen()
         d = mhdc.to_device(m, dev)
         n = m.n
-        for label, make in (("M-HDC n_b=%d" % nb, lambda: mhdc.MHDCMatrix.from_csr(*d, nb, 0.6)),
-                            ("CSR", lambda: mhdc.CSRMatrix.from_csr(*d))):
+        for label, fmt, make in (("M-HDC n_b=%d" % nb, "mhdc",
+                                  lambda: mhdc.MHDCMatrix.from_csr(*d, nb, 0.6)),
+                                 ("CSR", "csr", lambda: mhdc.CSRMatrix.from_csr(*d))):
+            if fmt not in formats:
+                continue
             h = make()
             inf = h.info()
             a_bytes = inf["bytes_alg"] - 16.0 * n
-            for k in (1, 2, 4, 8, 16):
+            for k in ks:
                 X = torch.rand((k, n), dtype=torch.float64, device=dev, generator=None)
                 Y = torch.empty_like(X)
                 t = timed(lambda: h.spmm(X, Y, s), args.steps, args.warmup, s)
@@ -79,7 +90,7 @@ def main():
             h.close()
         del d, m
         torch.cuda.empty_cache()
-    top = [r for r in rows if r["k"] == 16 and r["format"].startswith("M-HDC")][0]
+    top = ([r for r in rows if r["k"] == max(ks) and r["format"].startswith("M-HDC")] or rows)[0]
     print(json.dumps({"metric": "multi-RHS M-HDC SpMM GFLOP/s, FP64, 1xMI355X",
                       "value": top["gflops"], "unit": "GFLOP/s", "higher_is_better": True,
                       "dtype": "f64", "data": "synthetic (seeded stencil matrices, X ~ U[0,1))",
