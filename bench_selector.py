@@ -1,0 +1,89 @@
+"""Live check of the learned (theta, n_b) selector on the 200 held-out
+matrices: each matrix is regenerated from its stored seed and family, the
+selector (mhdc_select with the committed network and the byte-model judge)
+picks (theta, n_b), and three handles are timed back to back in
+interleaved rounds with mhdc_time_spmv: the selection, the policy
+(theta = 0.6, n_b = 256; Sec. 6.4.3) and the grid point that was fastest in
+the stored exhaustive sweep.  Re-timing the stored best removes the bias of
+taking a minimum over 40 noisy timings.
+
+    python bench_selector.py [--rounds 5] [--count 200]
+
+Prints one JSON line: mean t(selected)/t(best point), share within 5 %,
+the same for the policy, geometric-mean speed-up over the policy.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rounds", type=int, default=5)
+    ap.add_argument("--count", type=int, default=200)
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+
+    from paper_2105_04937_amd import learned, mhdc, synth
+    mhdc.lib()
+    recs = learned.load([os.path.join(learned.DATA_DIR, "test_0000-0199.jsonl.gz")])[:args.count]
+    net = learned.load_network()
+    rows = []
+    for r in recs:
+        fam = r["family"]
+        rp, ci, v = synth.stencil_matrix_gpu(fam["N"], r["seed"], points=fam["points"],
+                                             drop=fam["drop"], extra_per_row=fam["extra"])
+        n = rp.numel() - 1
+        g = torch.Generator(device="cuda")
+        g.manual_seed(r["seed"])
+        x = torch.rand(n, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        y = torch.empty_like(x)
+        h_sel, dec = mhdc.select(rp, ci, v, model=net, tolerance=learned.JUDGE_TOLERANCE)
+        best_key = min(r["us"], key=r["us"].get)
+        bth, bnb = best_key.split("/")
+        hs = {"selected": h_sel,
+              "policy": mhdc.MHDCMatrix.from_csr(rp, ci, v, learned.RULE[1], learned.RULE[0]),
+              "best": mhdc.MHDCMatrix.from_csr(rp, ci, v, int(bnb), float(bth))}
+        t = {k: float("inf") for k in hs}
+        for _ in range(args.rounds):
+            for k, h in hs.items():
+                t[k] = min(t[k], h.time_spmv(x, y))
+        for h in hs.values():
+            h.close()
+        rows.append(dict(id=r["id"], n=n, selected=learned.key(dec["theta"], dec["n_b"]),
+                         best=best_key, used_rule=bool(dec["used_rule"]),
+                         t_selected=round(t["selected"], 3), t_policy=round(t["policy"], 3),
+                         t_best=round(t["best"], 3)))
+        del rp, ci, v, x, y
+    ts = np.array([q["t_selected"] for q in rows])
+    tp = np.array([q["t_policy"] for q in rows])
+    tb = np.array([q["t_best"] for q in rows])
+    rep = dict(matrices=len(rows), rounds=args.rounds,
+               mean_selected_over_best=round(float(np.mean(ts / tb)), 4),
+               within_5pct_selected=round(float(np.mean(ts <= 1.05 * tb)), 3),
+               mean_policy_over_best=round(float(np.mean(tp / tb)), 4),
+               within_5pct_policy=round(float(np.mean(tp <= 1.05 * tb)), 3),
+               geomean_speedup_over_policy=round(float(np.exp(np.mean(np.log(tp / ts)))), 4),
+               selected_faster_than_best=round(float(np.mean(ts < tb)), 3),
+               used_rule=round(float(np.mean([q["used_rule"] for q in rows])), 3))
+    log(json.dumps(rep))
+    print(json.dumps({"metric": "learned selector, live re-timing on held-out matrices, "
+                                "FP64 M-HDC SpMV, 1xMI355X",
+                      "value": rep["mean_selected_over_best"], "unit": "t/t_best",
+                      "higher_is_better": False, "summary": rep, "rows": rows}))
+
+
+if __name__ == "__main__":
+    main()
