@@ -249,6 +249,17 @@ def main():
                       "gb_per_s": round(ic3["bytes_alg"] / tc3 / 1e9, 1), "us": round(tc3 * 1e6, 2)}
         res["hdc"] = {"gflops": round(2 * ih3["nnz"] / th3 / 1e9, 2), "us": round(th3 * 1e6, 2),
                       "alpha": round(ih3["alpha"], 4)}
+        # the learned selector's choice for this matrix (network + byte-model judge)
+        from paper_2105_04937_amd import learned
+        hsel, dec = mhdc.select(*d3, model=learned.load_network(),
+                                tolerance=learned.JUDGE_TOLERANCE)
+        ys = torch.empty_like(x3)
+        ts = time_steps(lambda: hsel.spmv(x3, ys, stream), args.steps // 2, args.warmup, stream)
+        res["mhdc_selected"] = {"theta": dec["theta"], "n_b": dec["n_b"],
+                                "used_rule": bool(dec["used_rule"]), "us": round(ts * 1e6, 2),
+                                "gflops": round(2 * m3.nnz / ts / 1e9, 2)}
+        log("selected theta=%.1f n_b=%d %8.3f us/step" % (dec["theta"], dec["n_b"], ts * 1e6))
+        hsel.close()
         best = min(v_["us"] for k_, v_ in res.items() if k_.startswith("mhdc"))
         res["speedup_best_mhdc_vs_csr"] = round(res["csr"]["us"] / best, 4)
         res["workload"] = "27-point 192^3, octant drops {0,.05,.1,.2,.3,.5,.7,.9}, +2 random/row"

@@ -1,13 +1,14 @@
-"""Live check of the learned (theta, n_b) selector on the 200 held-out
-matrices: each matrix is regenerated from its stored seed and family, the
-selector (mhdc_select with the committed network and the byte-model judge)
-picks (theta, n_b), and three handles are timed back to back in
+"""Live check of the learned (theta, n_b) selector on the 240 held-out
+matrices (200 of grid side 48..144, 40 of side 145..208): each matrix is
+regenerated from its stored seed and family, the selector (mhdc_select
+with the committed network and the byte-model judge) picks (theta, n_b),
+and three handles are timed back to back in
 interleaved rounds with mhdc_time_spmv: the selection, the policy
 (theta = 0.6, n_b = 256; Sec. 6.4.3) and the grid point that was fastest in
 the stored exhaustive sweep.  Re-timing the stored best removes the bias of
 taking a minimum over 40 noisy timings.
 
-    python bench_selector.py [--rounds 5] [--count 200]
+    python bench_selector.py [--rounds 5] [--count 240]
 
 Prints one JSON line: mean t(selected)/t(best point), share within 5 %,
 the same for the policy, geometric-mean speed-up over the policy.
@@ -30,7 +31,7 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rounds", type=int, default=5)
-    ap.add_argument("--count", type=int, default=200)
+    ap.add_argument("--count", type=int, default=240)
     args = ap.parse_args()
 
     import numpy as np
@@ -38,7 +39,8 @@ def main():
 
     from paper_2105_04937_amd import learned, mhdc, synth
     mhdc.lib()
-    recs = learned.load([os.path.join(learned.DATA_DIR, "test_0000-0199.jsonl.gz")])[:args.count]
+    recs = learned.load([os.path.join(learned.DATA_DIR, f) for f in
+                         ("test_0000-0199.jsonl.gz", "test_large_0000-0039.jsonl.gz")])[:args.count]
     net = learned.load_network()
     rows = []
     for r in recs:

@@ -5,7 +5,7 @@ theta = 0.6; Sec. 6.4.3) and leaves their choice open (Sec. 7).  Here:
 
 * collect: draw matrices of the stencil families (7/19/27-point grids with
   per-octant or global coupling drops and random extra columns, grid side
-  U{48..144}), compute the 66 census features (mhdc_features), and time the
+  U{48..144}, or U{145..208} for the *_large splits), compute the 66 census features (mhdc_features), and time the
   M-HDC SpMV for every (theta, n_b) of the grid theta in {0.5 .. 0.9}
   (Sec. 6.4.1's values) x n_b in {32 .. 4096} (mhdc_from_csr +
   mhdc_time_spmv).  One JSON line per matrix.
@@ -38,7 +38,8 @@ import numpy as np
 THETAS = (0.5, 0.6, 0.7, 0.8, 0.9)
 NBS = (32, 64, 128, 256, 512, 1024, 2048, 4096)
 RULE = (0.6, 256)
-SEED_BASE = {"train": 5000, "test": 9000}
+SEED_BASE = {"train": 5000, "test": 9000, "train_large": 7000, "test_large": 9500}
+SIDES = {"": (48, 144), "_large": (145, 208)}  # grid side range per split family
 LOSS_W = (25.0, 0.25)       # 1/0.2^2 for theta, 1/2^2 for log2 n_b
 HERE = os.path.dirname(os.path.abspath(__file__))
 DATA_DIR = os.path.join(HERE, "selector_data")
@@ -58,9 +59,12 @@ def load_network(path=WEIGHTS):
     return mhdc.MLP(np.load(path, allow_pickle=False))
 
 
-def draw_family(rng):
-    """Matrix parameters of one sample (drawn from its own seed)."""
-    N = int(rng.integers(48, 145))
+def draw_family(rng, large=False):
+    """Matrix parameters of one sample (drawn from its own seed); the large
+    splits draw grid sides 145..208 (3M to 9M rows, beyond the Infinity
+    Cache), the others 48..144."""
+    lo, hi = SIDES["_large" if large else ""]
+    N = int(rng.integers(lo, hi + 1))
     if rng.random() < 0.15:
         return dict(N=N, points=7, drop=0.0, extra=0, family="hepta")
     points = int(rng.choice([7, 19, 27]))
@@ -83,7 +87,7 @@ def collect(split, start, count, out_path):
         for i in range(start, start + count):
             t0 = time.time()
             seed = SEED_BASE[split] + i
-            fam = draw_family(np.random.default_rng(seed))
+            fam = draw_family(np.random.default_rng(seed), large=split.endswith("_large"))
             rp, ci, v = synth.stencil_matrix_gpu(fam["N"], seed, points=fam["points"],
                                                  drop=fam["drop"], extra_per_row=fam["extra"])
             n, nnz = rp.numel() - 1, ci.numel()
@@ -223,7 +227,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
-    c.add_argument("--split", choices=("train", "test"), required=True)
+    c.add_argument("--split", choices=tuple(SEED_BASE), required=True)
     c.add_argument("--start", type=int, default=0)
     c.add_argument("--count", type=int, default=100)
     c.add_argument("--out", required=True)
@@ -261,6 +265,8 @@ def main(argv=None):
                    mean_ratio=float(R[:, ks.index(prior)].mean()),
                    within_5pct=float(np.mean(R[:, ks.index(prior)] <= 1.05))),
                judge_tolerance_sweep=judge, train_set=rep_train)
+    if len(a.test) > 1:  # one summary per held-out file as well
+        rep["per_test_file"] = {os.path.basename(t): evaluate(net, load([t]))[0] for t in a.test}
     with open(os.path.join(a.out_dir, "eval_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep))
