@@ -361,3 +361,21 @@ def test_banded_stencil_dia_closed_forms(n, points):
         r0, r1 = ib * bl, min(n, ib * bl + bl)
         want = [o for o in offs if all(0 <= i + o < n for i in range(r0, r1))]
         assert list(mb.dia_off[mb.dia_ptr[ib]:mb.dia_ptr[ib + 1]]) == want
+
+
+@pytest.mark.parametrize("m", _small_cases()[:6], ids=lambda m: "n%d_s%d" % (m.n, m.meta["seed"]))
+def test_absmv_and_threads(m):
+    """|A||x| (the scale of the parity bound) equals numpy's |A| @ |x| exactly
+    on small-integer data; the row-parallel CSR loop gives the same bits as
+    the sequential one (each row is still summed in column order)."""
+    A = synth.dense_of(m)
+    xi = (np.arange(m.n, dtype=np.float64) % 5) - 2.0
+    vi = np.round(m.val * 3.0)
+    Ai = np.zeros_like(A)
+    for i in range(m.n):
+        for k in range(m.rowptr[i], m.rowptr[i + 1]):
+            Ai[i, m.colind[k]] = vi[k]
+    assert np.array_equal(oracle.csr_absmv(m.rowptr, m.colind, vi, xi), np.abs(Ai) @ np.abs(xi))
+    x = synth.vector(m.n, 3)
+    assert np.array_equal(oracle.csr_spmv(m.rowptr, m.colind, m.val, x, 4),
+                          oracle.csr_spmv(m.rowptr, m.colind, m.val, x, 1))
