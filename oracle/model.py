@@ -3,7 +3,7 @@
 Byte counts V = V_A + V_x + V_y (Eq. 4) for the CSR, DIA, B-DIA, B-HDC and
 M-HDC kernels, with b_fp = 8 and b_int = 4 (FP64 values, INT32 indices), and
 the speed-up expressions the paper derives from them (Eqs. 3, 9, 16, 19, 28).
-Only tests and the benchmark's reporting read this module.
+Only the tests read this module.
 """
 from __future__ import annotations
 
