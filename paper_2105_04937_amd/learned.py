@@ -251,11 +251,14 @@ def main(argv=None):
     np.save(os.path.join(a.out_dir, "weights.npy"), net.params())
     rep, rows = evaluate(net, test)
     rep_train, _ = evaluate(net, recs)
-    judge = {}
+    # the judge's tolerance is chosen on the training set; the held-out sweep
+    # is reported beside it
+    judge, judge_train = {}, {}
     for tol in (0.0, 0.05, 0.10, 0.25, 1e9):
-        r_, _ = evaluate(net, test, tolerance=tol)
-        judge["%g" % tol] = {k: r_[k] for k in ("within_5pct_selected", "mean_ratio_selected",
-                                                "used_network")}
+        for dst, rs in ((judge, test), (judge_train, recs)):
+            r_, _ = evaluate(net, rs, tolerance=tol)
+            dst["%g" % tol] = {k: r_[k] for k in ("within_5pct_selected", "mean_ratio_selected",
+                                                  "used_network")}
     ks = list(test[0]["us"])
     R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in test])
     rep.update(judge_tolerance=JUDGE_TOLERANCE,
@@ -264,7 +267,8 @@ def main(argv=None):
                prior=prior, prior_fixed_on_test=dict(
                    mean_ratio=float(R[:, ks.index(prior)].mean()),
                    within_5pct=float(np.mean(R[:, ks.index(prior)] <= 1.05))),
-               judge_tolerance_sweep=judge, train_set=rep_train)
+               judge_tolerance_sweep=judge, judge_tolerance_sweep_train=judge_train,
+               train_set=rep_train)
     if len(a.test) > 1:  # one summary per held-out file as well
         rep["per_test_file"] = {os.path.basename(t): evaluate(net, load([t]))[0] for t in a.test}
     with open(os.path.join(a.out_dir, "eval_report.json"), "w") as f:
