@@ -95,6 +95,9 @@ typedef struct {
     double alpha, beta;
     double bytes_alg, bytes_paper, rp_est;
     int32_t rows_per_lane, wg_size, xcd_remap, csr_mode, rhs_group; /* launch shape */
+    double row_repeat;   /* share of the CSR part's nonempty rows whose column
+                            offsets (col - row) repeat the previous row's, in
+                            length and order; 0 for an empty CSR part */
 } mhdc_info;
 
 /* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
@@ -110,11 +113,12 @@ typedef struct {
  * right-hand side and 2 for several; rhs_group in {0, 1, 2, 4, 8, 16}:
  * right-hand sides processed per pass over a tile (0 = all, up to 16; a
  * further pass reads the tile's share of A again from the caches).  Every
- * variant gives the same bits.  A new handle starts with {1, 256, 16, 0, 0}
+ * variant gives the same bits.  A new handle starts with {1, 256, 16, c, 0}
  * for n >= 2^20 rows ({2, 256, 8, 0, 0} when it averages under 4 stored
  * entries per row and n_b is a multiple of 128 or the whole matrix) and
- * {1, 64, 0, 0, 0} below.  Set before use, not while spmv calls on the
- * handle are in flight. */
+ * {1, 64, 0, c, 0} below, where c = 2 if row_repeat >= 0.5 (mhdc_info),
+ * else 0.  Set before use, not while spmv calls on the handle are in
+ * flight. */
 typedef struct {
     int32_t rows_per_lane;
     int32_t wg_size;

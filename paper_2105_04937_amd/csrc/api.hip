@@ -16,7 +16,7 @@ thread_local std::string t_msg;
 std::atomic<int32_t> g_fail_countdown{0};
 }  // namespace
 
-mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz)
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat)
 {
     // Large matrices: 256-lane workgroups, runs of 4096 consecutive rows per
     // XCD: a tile's neighbours, whose x entries it also reads through the
@@ -29,14 +29,22 @@ mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz)
     // 256^3 heptadiagonal and the 192^3 partially diagonal cases the default
     // is within 4% of the best of 7 shapes for every n_b tried.
     // Small matrices: 64-lane workgroups so that the 256 CUs get work.
+    // With one row per lane, a CSR part whose rows mostly repeat the previous
+    // row's column offsets (stencils) stages values and columns and lets
+    // each lane gather x for its own rows (csr_mode 2): the wavefront's
+    // gathers then hit neighbouring elements (256^3 7-point CSR: 338 us
+    // against 361 us with staged products; on rows of mixed structure the
+    // staged products are faster, 545 against 596 us on the 192^3 partially
+    // diagonal CSR).
+    const int32_t mode1 = row_repeat >= 0.5 ? 2 : 0;
     if ((int64_t)n >= 256LL * 2 * 2048) {
         const bool short_rows = nnz > 0 && nnz < 4LL * n;
         const bool v2_uniform = n_b <= 0 || n_b >= n || n_b % 128 == 0;
         if (short_rows && v2_uniform)
             return mhdc_launch{2, 256, 8, 0, 0};
-        return mhdc_launch{1, 256, 16, 0, 0};
+        return mhdc_launch{1, 256, 16, mode1, 0};
     }
-    return mhdc_launch{1, 64, 0, 0, 0};
+    return mhdc_launch{1, 64, 0, mode1, 0};
 }
 
 namespace {
@@ -73,6 +81,7 @@ void fill_info(const BdcMatrix &m, mhdc_info *o)
     o->xcd_remap = m.launch.xcd_remap;
     o->csr_mode = m.launch.csr_mode;
     o->rhs_group = m.launch.rhs_group;
+    o->row_repeat = m.row_repeat;
 }
 
 int check_theta_nb(int32_t n, int32_t n_b, double theta, bool need_nb)
@@ -98,7 +107,7 @@ H *make_handle(int kind, int32_t n, int32_t n_b, double theta)
     h->m.n = n;
     h->m.n_b = n_b;
     h->m.theta = theta;
-    h->m.launch = default_launch(n, n_b, 0);
+    h->m.launch = default_launch(n, n_b, 0, 0.0);
     (void)hipGetDevice(&h->m.device);
     return h;
 }
@@ -111,7 +120,7 @@ H *finish(H *h, int rc)
         delete h;
         return nullptr;
     }
-    h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz);
+    h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz, h->m.row_repeat);
     return h;
 }
 

@@ -273,6 +273,42 @@ __global__ __launch_bounds__(CV_WG) void k_rem_mask(int32_t n, int64_t words,
     }
 }
 
+// One lane per row of a CSR-shaped pair (ptr, col): cnt[0] counts the rows
+// with entries, cnt[1] those of them whose column offsets col - row repeat
+// the previous row's (same length, same offsets in order).  Where most rows
+// repeat (stencils), the lanes of a wavefront gathering x for their own rows
+// read neighbouring elements.
+__global__ __launch_bounds__(CV_WG) void k_row_repeat(int32_t n, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      unsigned long long *cnt)
+{
+    uint32_t ne = 0, rep = 0;
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int32_t b1 = ptr[i], e1 = ptr[i + 1];
+        if (e1 == b1)
+            continue;
+        ne++;
+        if (i == 0)
+            continue;
+        const int32_t b0 = ptr[i - 1];
+        if (b1 - b0 != e1 - b1)
+            continue;
+        bool same = true;
+        for (int32_t e = 0; e < e1 - b1 && same; e++)
+            same = (int64_t)col[b1 + e] - i == (int64_t)col[b0 + e] - (i - 1);
+        rep += same ? 1u : 0u;
+    }
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        ne += __shfl_xor(ne, sh, 64);
+        rep += __shfl_xor(rep, sh, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(cnt, (unsigned long long)ne);
+        atomicAdd(cnt + 1, (unsigned long long)rep);
+    }
+}
+
 // ---------------------------------------------------------------- decode
 __global__ __launch_bounds__(CV_WG) void k_decode_count(int32_t n, int32_t n_b,
                                                         const int32_t *__restrict__ dia_ptr,
@@ -409,6 +445,29 @@ int validate_csr(int32_t n, const int32_t *rowptr, const int32_t *colind, const 
                              "column index out of range, unsorted or duplicated in a row");
     }
     *nnz_out = nnz;
+    return MHDC_OK;
+}
+
+// Share of the CSR part's nonempty rows that repeat the previous row's
+// column offsets (k_row_repeat); 0 for an empty CSR part.
+int row_repeat_share(int32_t n, const int32_t *ptr, const int32_t *col, double *share)
+{
+    *share = 0.0;
+    if (n <= 1)
+        return MHDC_OK;
+    unsigned long long *cnt = nullptr;
+    int rc = dmalloc((void **)&cnt, 2 * sizeof(unsigned long long), "row repeat counts");
+    if (rc)
+        return rc;
+    TempSet tmp;
+    tmp.add(cnt);
+    MHDC_HIP_CHECK(hipMemset(cnt, 0, 2 * sizeof(unsigned long long)));
+    k_row_repeat<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, ptr, col, cnt);
+    if ((rc = launch_ok("row repeat")))
+        return rc;
+    unsigned long long h[2] = {0, 0};
+    MHDC_HIP_CHECK(hipMemcpy(h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+    *share = h[0] > 0 ? (double)h[1] / (double)h[0] : 0.0;
     return MHDC_OK;
 }
 
@@ -605,6 +664,8 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
             dfree(m.rem_mask);
             m.rem_mask = nullptr;
         }
+        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat)))
+            return rc;
     }
     return sync_ok("conversion");
 }
@@ -634,6 +695,8 @@ int build_csr(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const 
                                  hipMemcpyDeviceToDevice));
         MHDC_HIP_CHECK(hipMemcpy(m.rem_val, val, sizeof(double) * (size_t)nnz,
                                  hipMemcpyDeviceToDevice));
+        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat)))
+            return rc;
     }
     return sync_ok("csr copy");
 }

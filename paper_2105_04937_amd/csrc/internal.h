@@ -34,6 +34,9 @@ struct BdcMatrix {
     // tests its bits in this small, cache-resident array instead of
     // fetching rem_ptr from HBM before it can start on its diagonals.
     uint32_t *rem_mask = nullptr;
+    // Share of the CSR part's nonempty rows whose column offsets repeat the
+    // previous row's (0 when the CSR part is empty); picks the CSR mode.
+    double row_repeat = 0.0;
     int device = 0;
     mhdc_launch launch{2, 256, 0, 0, 0};
 };
@@ -90,7 +93,7 @@ int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
                        int64_t *total, hipStream_t stream);
 
 // api.hip: handle creation shared with the autotuner
-mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz);
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat);
 
 }  // namespace mhdc
 

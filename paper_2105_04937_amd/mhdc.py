@@ -35,7 +35,8 @@ class Info(ctypes.Structure):
                 ("bytes_alg", ctypes.c_double), ("bytes_paper", ctypes.c_double),
                 ("rp_est", ctypes.c_double), ("rows_per_lane", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("csr_mode", ctypes.c_int32), ("rhs_group", ctypes.c_int32)]
+                ("csr_mode", ctypes.c_int32), ("rhs_group", ctypes.c_int32),
+                ("row_repeat", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

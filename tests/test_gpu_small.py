@@ -284,6 +284,59 @@ def test_error_paths():
         assert e.value.name == "MHDC_ERR_NOT_SUPPORTED"
 
 
+def _row_repeat(ptr, col):
+    """Share of the nonempty rows whose column offsets repeat the previous
+    row's, counted row by row on the host."""
+    ptr = np.asarray(ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    nonempty = rep = 0
+    for i in range(len(ptr) - 1):
+        a, b = ptr[i], ptr[i + 1]
+        if a == b:
+            continue
+        nonempty += 1
+        if i > 0:
+            p = ptr[i - 1]
+            if a - p == b - a and np.array_equal(col[a:b] - i, col[p:a] - (i - 1)):
+                rep += 1
+    return rep / nonempty if nonempty else 0.0
+
+
+def test_row_repeat_picks_csr_mode():
+    """row_repeat of the CSR part equals the host count, and the default
+    launch stages values and columns (csr_mode 2) exactly when at least half
+    the nonempty rows repeat; results are the same bits either way."""
+    cases = [("7-point 12^3", synth.heptadiagonal(12, 1), True),
+             ("27-point 10^3 octant drops", synth.partially_diagonal(10, 2, drop=synth.OCTANT_DROP),
+              False),
+             ("random 300", synth.random_csr(300, 5, density=0.02), False),
+             ("banded 3-point", synth.banded_stencil(4000, 3, 1), True)]
+    for name, m, regular in cases:
+        say("case: row repeat %s" % name)
+        rp, ci, v = dev(m)
+        want = _row_repeat(m.rowptr, m.colind)
+        assert (want >= 0.5) == regular, (name, want)
+        cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
+        inf = cs.info()
+        assert inf["row_repeat"] == want, (name, inf["row_repeat"], want)
+        assert inf["csr_mode"] == (2 if inf["rows_per_lane"] == 1 and regular else 0)
+        x = synth.vector(m.n, 7)
+        xd = torch.from_numpy(x).cuda()
+        y_def = cs.spmv(xd).cpu().numpy()
+        cs.set_launch(inf["rows_per_lane"], inf["wg_size"], inf["xcd_remap"], 1, 0)
+        assert_same_bits(cs.spmv(xd).cpu().numpy(), y_def, name)
+        cs.close()
+        h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 64, 0.6)
+        t = h.export()
+        want_r = _row_repeat(t["rem_ptr"].cpu().numpy(), t["rem_col"].cpu().numpy())
+        inf = h.info()
+        assert inf["row_repeat"] == want_r, (name, inf["row_repeat"], want_r)
+        if inf["R"] == 0:
+            assert inf["row_repeat"] == 0.0
+        assert inf["csr_mode"] == (2 if inf["rows_per_lane"] == 1 and want_r >= 0.5 else 0)
+        h.close()
+
+
 def test_allocation_failure_leaks_nothing():
     """Fail the k-th device allocation of a conversion for every k: each
     attempt reports MHDC_ERR_OOM and returns all memory it took."""
