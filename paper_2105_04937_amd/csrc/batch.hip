@@ -61,7 +61,7 @@ template <int WG, int KC>
 __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *lds)
 {
     if constexpr (KC > 1) {
-        spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);
+        spmv_tile<WG, 1, KC, true, true, true, 1>(it.a, local, lds);
     } else {
         if (it.rg)
             spmv_tile<WG, 1, KC, true, true, true>(it.a, local, lds);

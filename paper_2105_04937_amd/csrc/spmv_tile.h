@@ -112,8 +112,9 @@ struct TileShape {
     // remainder entries staged per chunk
     static constexpr int CH = RG ? WG * 8 : ((WG * 8 / KC) < WG ? WG : WG * 8 / KC);
     static constexpr int LDS_BYTES = RG ? CH * 12 : KC * CH * 8;
-    // diagonals processed together in the uniform DIA path
-    static constexpr int U = KC == 1 ? 8 : (KC <= 4 ? 2 : 1);
+    // diagonals processed together in the uniform DIA path (8 and 16
+    // columns: the U8 argument of spmv_tile_cols)
+    static constexpr int U = KC == 1 ? 8 : 2;
     // remainder entries gathered together per row in the RG variant
     static constexpr int UR = KC == 1 ? 4 : (KC <= 4 ? 2 : 1);
 };
@@ -121,7 +122,10 @@ struct TileShape {
 // HAS_DIA / HAS_REM compile the DIA part / the CSR part in (a kernel's
 // register budget is that of everything it contains); a.has_dia and
 // a.has_rem still switch them per matrix at run time.
-template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
+// U8: diagonals in flight in the uniform DIA path for 8 and 16 columns (two
+// in the single-matrix kernel; one in the batched kernel, which keeps four
+// waves per SIMD and would spill with two).
+template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG, int U8 = 2>
 __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds,
                                       const double *__restrict__ Xg, double *__restrict__ Yg,
                                       int32_t kc_n)
@@ -132,7 +136,7 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
     constexpr int T = WG * V;
     constexpr int CH = Shape::CH;
     // eight diagonals in flight for pure DIA tiles, four next to a CSR part
-    constexpr int U = (KC == 1 && HAS_REM) ? 4 : Shape::U;
+    constexpr int U = (KC == 1 && HAS_REM) ? 4 : (KC >= 8 ? U8 : Shape::U);
     constexpr int UR = Shape::UR;
     const int n = a.n;
     const int64_t tile_base = tile * T;
@@ -374,13 +378,13 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
 
 // All right-hand sides of the tile, KC columns per pass (the tile's share
 // of A is read again from the caches for every further pass).
-template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
+template <int WG, int V, int KC, bool HAS_DIA, bool HAS_REM, bool RG, int U8 = 2>
 __device__ inline void spmv_tile(const SpmvArgs &a, int64_t tile, void *lds)
 {
     for (int32_t r0 = 0; r0 < a.k; r0 += KC) {
         const int32_t kc_n = a.k - r0 < KC ? a.k - r0 : KC;
-        spmv_tile_cols<WG, V, KC, HAS_DIA, HAS_REM, RG>(a, tile, lds, a.X + r0 * a.ldx,
-                                                        a.Y + r0 * a.ldy, kc_n);
+        spmv_tile_cols<WG, V, KC, HAS_DIA, HAS_REM, RG, U8>(a, tile, lds, a.X + r0 * a.ldx,
+                                                            a.Y + r0 * a.ldy, kc_n);
     }
 }
 
