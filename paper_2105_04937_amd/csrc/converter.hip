@@ -294,18 +294,32 @@ __global__ __launch_bounds__(CV_WG) void k_row_repeat(int32_t n, const int32_t *
         const int32_t b0 = ptr[i - 1];
         if (b1 - b0 != e1 - b1)
             continue;
+        // no early exit: the loads of a row issue together
         bool same = true;
-        for (int32_t e = 0; e < e1 - b1 && same; e++)
-            same = (int64_t)col[b1 + e] - i == (int64_t)col[b0 + e] - (i - 1);
+        for (int32_t e = 0; e < e1 - b1; e++)
+            same &= (int64_t)col[b1 + e] - i == (int64_t)col[b0 + e] - (i - 1);
         rep += same ? 1u : 0u;
     }
+    // one pair of atomics per workgroup (on a few thousand workgroups):
+    // per-wavefront atomics on the two counters serialised for milliseconds
     for (int sh = 32; sh >= 1; sh >>= 1) {
         ne += __shfl_xor(ne, sh, 64);
         rep += __shfl_xor(rep, sh, 64);
     }
+    __shared__ unsigned long long s_sum[2][CV_WG / 64];
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(cnt, (unsigned long long)ne);
-        atomicAdd(cnt + 1, (unsigned long long)rep);
+        s_sum[0][threadIdx.x >> 6] = ne;
+        s_sum[1][threadIdx.x >> 6] = rep;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int w = 0; w < CV_WG / 64; w++) {
+            a += s_sum[0][w];
+            b += s_sum[1][w];
+        }
+        atomicAdd(cnt, a);
+        atomicAdd(cnt + 1, b);
     }
 }
 
@@ -462,7 +476,7 @@ int row_repeat_share(int32_t n, const int32_t *ptr, const int32_t *col, double *
     TempSet tmp;
     tmp.add(cnt);
     MHDC_HIP_CHECK(hipMemset(cnt, 0, 2 * sizeof(unsigned long long)));
-    k_row_repeat<<<grid_for(n, CV_WG, 1 << 16), CV_WG, 0, 0>>>(n, ptr, col, cnt);
+    k_row_repeat<<<grid_for(n, CV_WG, 1 << 12), CV_WG, 0, 0>>>(n, ptr, col, cnt);
     if ((rc = launch_ok("row repeat")))
         return rc;
     unsigned long long h[2] = {0, 0};
