@@ -337,6 +337,35 @@ def test_row_repeat_picks_csr_mode():
         h.close()
 
 
+def test_conversion_and_spmv_are_deterministic():
+    """Two conversions of the same matrix give the same arrays byte for byte,
+    and two products the same bits, whatever order the census atomics took:
+    blocks small enough for the LDS hash (n_b = 32) and large enough for the
+    global table (n_b = 4096, ~90k entries per block), HDC and CSR."""
+    m = synth.partially_diagonal(24, 5, drop=synth.OCTANT_DROP)
+    rp, ci, v = dev(m)
+    x = torch.from_numpy(synth.vector(m.n, 5)).cuda()
+    for nb in (32, 4096):
+        say("case: determinism n_b=%d" % nb)
+        runs = []
+        for _ in range(2):
+            h = mhdc.MHDCMatrix.from_csr(rp, ci, v, nb, 0.6)
+            t = {k: a.cpu().numpy() for k, a in h.export().items()}
+            t["y"] = h.spmv(x).cpu().numpy()
+            h.close()
+            runs.append(t)
+        for k in runs[0]:
+            assert_same_bits(runs[1][k], runs[0][k], "n_b=%d %s" % (nb, k))
+    for make in (lambda: mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6),
+                 lambda: mhdc.CSRMatrix.from_csr(rp, ci, v)):
+        ys = []
+        for _ in range(2):
+            h = make()
+            ys.append(h.spmv(x).cpu().numpy())
+            h.close()
+        assert_same_bits(ys[1], ys[0], "HDC/CSR product")
+
+
 def test_allocation_failure_leaks_nothing():
     """Fail the k-th device allocation of a conversion for every k: each
     attempt reports MHDC_ERR_OOM and returns all memory it took."""
