@@ -321,7 +321,9 @@ int mhdc_mlp_loss_grad(mhdc_mlp m, const float *X, const float *T, int32_t B,
                        hipStream_t stream);
 /* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) on
  * minibatches of B rows: step s uses rows order[s*B .. s*B+B) of X[N][66]
- * and targets T[N][2] (device arrays; the caller draws the order).
+ * and targets T[N][2] (device arrays; the caller draws the order).  Every
+ * order entry is checked to lie in [0, N) before training (INVALID_ARG
+ * otherwise).
  * loss_hist[s] receives each step's loss.  One step is captured once as a
  * HIP graph and replayed.  Synchronous. */
 int mhdc_mlp_train(mhdc_mlp m, const float *X, const float *T, int32_t N,

@@ -219,6 +219,16 @@ __global__ void k_steps_inc(int32_t *step, int32_t *local_step)
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
+// bad = 1 if an entry of order[0..count) is outside [0, N)
+__global__ __launch_bounds__(TW) void k_check_order(const int32_t *__restrict__ order, int64_t count,
+                                                    int32_t N, int32_t *bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * TW + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * TW)
+        if (order[i] < 0 || order[i] >= N)
+            *bad = 1;
+}
+
 // rows order[local_step*B + r] of X/T -> minibatch buffers
 __global__ __launch_bounds__(TW) void k_gather(const float *__restrict__ X,
                                                const float *__restrict__ T,
@@ -471,6 +481,26 @@ int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const 
     int rc = ensure_buffers(M, B);
     if (rc)
         return rc;
+    {
+        // every minibatch row index must name a row of X/T
+        int32_t *bad = nullptr;
+        if ((rc = dmalloc((void **)&bad, sizeof(int32_t), "order check flag")))
+            return rc;
+        const int64_t count = steps * (int64_t)B;
+        k_zero_i32<<<1, 1, 0, stream>>>(bad);
+        const int64_t blocks = (count + TW - 1) / TW;
+        k_check_order<<<(unsigned)(blocks < 4096 ? blocks : 4096), TW, 0, stream>>>(order, count, N,
+                                                                                   bad);
+        int32_t h = 0;
+        hipError_t e = hipMemcpyAsync(&h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(stream);
+        dfree(bad);
+        if (e != hipSuccess)
+            return set_error(MHDC_ERR_HIP, std::string("mlp train: ") + hipGetErrorString(e));
+        if (h)
+            return set_error(MHDC_ERR_INVALID_ARG, "order holds a row index outside [0, N)");
+    }
     // capture one step: gather, forward, loss, backward, Adam, counters
     hipStream_t cs = nullptr;
     MHDC_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

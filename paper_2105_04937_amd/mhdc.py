@@ -208,6 +208,8 @@ class _Matrix:
             raise ValueError("x has %d entries, expected %d" % (x.numel(), self.n))
         if y is None:
             y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        if y.numel() != self.n:
+            raise ValueError("y has %d entries, expected %d" % (y.numel(), self.n))
         _check(self._fn("spmv")(self._h, _dptr(x, torch.float64, "x"),
                                 _dptr(y, torch.float64, "y"), _stream(stream)))
         return y
@@ -216,6 +218,8 @@ class _Matrix:
         """Mean microseconds per spmv, timed from C with HIP events (M-HDC)."""
         if self.kind != KIND_MHDC:
             raise TypeError("time_spmv takes an M-HDC handle")
+        if x.numel() != self.n or y.numel() != self.n:
+            raise ValueError("x and y must hold %d entries" % self.n)
         us = ctypes.c_float(0)
         _check(lib().mhdc_time_spmv(self._h, _dptr(x, torch.float64, "x"),
                                     _dptr(y, torch.float64, "y"), _stream(stream), ctypes.byref(us)))
@@ -229,6 +233,8 @@ class _Matrix:
         k = X.shape[0]
         if Y is None:
             Y = torch.empty((k, self.n), dtype=torch.float64, device=X.device)
+        if tuple(Y.shape) != (k, self.n):
+            raise ValueError("Y must have shape (%d, %d)" % (k, self.n))
         _check(self._fn("spmm")(self._h, _dptr(X, torch.float64, "X"), self.n,
                                 _dptr(Y, torch.float64, "Y"), self.n, k, _stream(stream)))
         return Y
@@ -323,6 +329,8 @@ class HDCMatrix(_Matrix):
             raise ValueError("x has %d entries, expected %d" % (x.numel(), self.n))
         if y is None:
             y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        if y.numel() != self.n:
+            raise ValueError("y has %d entries, expected %d" % (y.numel(), self.n))
         _check(lib().hdc_spmv_unblocked(self._h, _dptr(x, torch.float64, "x"),
                                         _dptr(y, torch.float64, "y"), _stream(stream)))
         return y
@@ -470,14 +478,22 @@ class MLP:
         _check(lib().mhdc_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
         return p
 
+    @staticmethod
+    def _rows(X):
+        if X.dim() != 2 or X.shape[1] != MLP_IN:
+            raise ValueError("X must have shape (B, %d)" % MLP_IN)
+        return X.shape[0]
+
     def forward(self, X, stream=None):
-        B = X.shape[0]
+        B = self._rows(X)
         out = torch.empty((B, 2), dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_forward(self._h, _dptr(X, torch.float32, "X"), B,
                                       _dptr(out, torch.float32, "out"), _stream(stream)))
         return out
 
     def loss_grad(self, X, T, w=(1.0, 1.0), stream=None):
+        if tuple(T.shape) != (self._rows(X), 2):
+            raise ValueError("T must have shape (B, 2)")
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
         grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_loss_grad(self._h, _dptr(X, torch.float32, "X"),
@@ -488,6 +504,10 @@ class MLP:
 
     def train(self, X, T, order, steps, B, lr, w=(1.0, 1.0), stream=None):
         """Adam over minibatches order[s*B:(s+1)*B] (int32 device tensor)."""
+        if tuple(T.shape) != (self._rows(X), 2):
+            raise ValueError("T must have shape (N, 2)")
+        if order.numel() < int(steps) * int(B):
+            raise ValueError("order must hold steps * B row indices")
         hist = torch.empty(int(steps), dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_train(self._h, _dptr(X, torch.float32, "X"),
                                     _dptr(T, torch.float32, "T"), X.shape[0],
@@ -498,7 +518,7 @@ class MLP:
 
     def decide(self, X, stream=None):
         """(theta, n_b, ok) device tensors for B feature rows."""
-        B = X.shape[0]
+        B = self._rows(X)
         th = torch.empty(B, dtype=torch.float64, device=X.device)
         nb = torch.empty(B, dtype=torch.int32, device=X.device)
         ok = torch.empty(B, dtype=torch.int32, device=X.device)
@@ -533,6 +553,8 @@ def select(rowptr, colind, val, model=None, tolerance=0.25):
 
 def stream_direct(A, B, C, stream=None):
     """C += A * B elementwise (memory benchmark, Sec. 6.2)."""
+    if A.numel() != C.numel() or B.numel() != C.numel():
+        raise ValueError("A, B and C must hold the same number of elements")
     _check(lib().mhdc_stream_direct(C.numel(), _dptr(A, torch.float64, "A"),
                                     _dptr(B, torch.float64, "B"), _dptr(C, torch.float64, "C"),
                                     _stream(stream)))
@@ -541,6 +563,8 @@ def stream_direct(A, B, C, stream=None):
 
 def stream_indirect(A, B, I, C, stream=None):
     """C += A * B[I] elementwise (memory benchmark, Sec. 6.2)."""
+    if A.numel() != C.numel() or B.numel() != C.numel() or I.numel() != C.numel():
+        raise ValueError("A, B, I and C must hold the same number of elements")
     _check(lib().mhdc_stream_indirect(C.numel(), _dptr(A, torch.float64, "A"),
                                       _dptr(B, torch.float64, "B"), _dptr(I, torch.int32, "I"),
                                       _dptr(C, torch.float64, "C"), _stream(stream)))

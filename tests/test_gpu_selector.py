@@ -89,6 +89,15 @@ def test_training_matches_oracle_adam_and_is_deterministic():
     net2 = mhdc.MLP(p0)
     net2.train(Xd, Td, od, steps, B, lr, w=(25.0, 0.1))
     assert np.array_equal(net2.params().view(np.int32), p_gpu.view(np.int32))
+    # a row index outside [0, N) is rejected before any step runs
+    for badval in (N, -1):
+        bad = od.clone()
+        bad[B + 3] = badval
+        net3 = mhdc.MLP(p0)
+        with pytest.raises(mhdc.MhdcError) as ei:
+            net3.train(Xd, Td, bad, steps, B, lr, w=(25.0, 0.1))
+        assert ei.value.name == "MHDC_ERR_INVALID_ARG"
+        assert np.array_equal(net3.params().view(np.int32), p0.view(np.int32))
 
 
 def test_training_reduces_loss():

@@ -282,6 +282,15 @@ def test_error_paths():
         with pytest.raises(mhdc.MhdcError) as e:
             h.set_launch(1, 256, remap)
         assert e.value.name == "MHDC_ERR_NOT_SUPPORTED"
+    # outputs of the wrong size are refused by the binding before any launch
+    x = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        h.spmv(x, torch.zeros(m.n - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        h.spmm(torch.zeros((2, m.n), dtype=torch.float64, device="cuda"),
+               torch.zeros((2, m.n - 1), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        mhdc.stream_direct(x, x[:-1], torch.zeros_like(x))
 
 
 def _row_repeat(ptr, col):
