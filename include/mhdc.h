@@ -116,9 +116,9 @@ typedef struct {
  * variant gives the same bits.  A new handle starts with {1, 256, 16, c, 0}
  * for n >= 2^20 rows ({2, 256, 8, 0, 0} when it averages under 4 stored
  * entries per row and n_b is a multiple of 128 or the whole matrix) and
- * {1, 64, 0, c, 0} below, where c = 2 if row_repeat >= 0.5 (mhdc_info),
- * else 0.  Set before use, not while spmv calls on the handle are in
- * flight. */
+ * {1, 64, 0, c, 0} below, where c = 2 for a handle without DIA part (CSR,
+ * or K = 0) whose row_repeat (mhdc_info) is at least 0.5, else 0.  Set
+ * before use, not while spmv calls on the handle are in flight. */
 typedef struct {
     int32_t rows_per_lane;
     int32_t wg_size;
