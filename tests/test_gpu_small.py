@@ -191,6 +191,35 @@ def test_multi_rhs(k):
                 assert_oracle_bits(Y[r], want, "rhs %d" % r)
 
 
+def test_spmm_padded_leading_dimensions():
+    """mhdc_spmm / hdc_spmm / csr_spmm with ldx, ldy > n through the C-ABI:
+    every column equals its own spmv bit for bit, the padding rows of Y
+    keep their sentinel, and ldx < n is refused."""
+    m = synth.partially_diagonal(12, 8, drop=0.1)
+    rp, ci, v = dev(m)
+    n, k = m.n, 5
+    ldx, ldy = n + 5, n + 3
+    X = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, size=(k, ldx))).cuda()
+    L = mhdc.lib()
+    s = torch.cuda.current_stream()
+    for make, fn in ((lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, 32, 0.6), L.mhdc_spmm),
+                     (lambda: mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6), L.hdc_spmm),
+                     (lambda: mhdc.CSRMatrix.from_csr(rp, ci, v), L.csr_spmm)):
+        h = make()
+        say("case: padded ld %s" % type(h).__name__)
+        Y = torch.full((k, ldy), 7.25, dtype=torch.float64, device="cuda")
+        assert fn(h._h, X.data_ptr(), ldx, Y.data_ptr(), ldy, k, s.cuda_stream) == 0
+        torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        for r in range(k):
+            y1 = h.spmv(X[r, :n].contiguous()).cpu().numpy()
+            assert_same_bits(Yh[r, :n], y1, "column %d" % r)
+            assert np.all(Yh[r, n:] == 7.25)
+        assert mhdc.ERRORS[fn(h._h, X.data_ptr(), n - 1, Y.data_ptr(), ldy, k,
+                              s.cuda_stream)] == "MHDC_ERR_INVALID_ARG"
+        h.close()
+
+
 def test_degenerate_shapes():
     say("case: degenerate shapes")
     # n = 0
