@@ -3,8 +3,9 @@
 // Steps (M-HDC, Sec. 4.3; HDC, Sec. 3.4), each a HIP kernel:
 //   1. validate the CSR arrays (one lane per row, error bits in a flag);
 //   2. census: for each row block count the nonzeros of every offset
-//      d = j - i in an open-addressing hash table (LDS when the block holds
-//      fewer than CENSUS_LDS_SLOTS entries, else a per-block region of a
+//      d = j - i in an open-addressing hash table (in LDS, 512, 2048 or
+//      8192 slots, the smallest that holds the largest block, when the
+//      block holds fewer entries than that, else a per-block region of a
 //      global table); only integer atomics on counts, so the counted set
 //      does not depend on the order of the atomics;
 //   3. select offsets with count/rows >= theta and order each block's list
@@ -81,6 +82,10 @@ __global__ __launch_bounds__(CV_WG) void k_block_max(int32_t n, int32_t n_b, int
 //   Kb[ib] = number kept, sel_tmp[e0 .. e0+Kb) = kept offsets ascending,
 //   with e0 = rowptr[ib*n_b] (a block keeps at most its entry count).
 // mode 1 (HDC census): add each block's counts into hdc_count[d + n - 1].
+// SLOTS: LDS hash-table slots, the smallest of 512 / 2048 / 8192 that holds
+// the largest block (small tables leave LDS for more resident workgroups:
+// with 8192 slots only two fit per CU).
+template <int SLOTS>
 __global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n_b, int64_t n_blk,
                                                   const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ colind,
@@ -89,8 +94,10 @@ __global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n
                                                   int32_t *gkeys, int32_t *gcnts,
                                                   int32_t *hdc_count)
 {
-    __shared__ int32_t s_keys[CENSUS_LDS_SLOTS];
-    __shared__ int32_t s_cnts[CENSUS_LDS_SLOTS];
+    static_assert(SLOTS >= 64 && SLOTS <= CENSUS_LDS_SLOTS && (SLOTS & (SLOTS - 1)) == 0,
+                  "table slots");
+    __shared__ int32_t s_keys[SLOTS];
+    __shared__ int32_t s_cnts[SLOTS];
     __shared__ int32_t s_nsel;
 
     for (int64_t ib = blockIdx.x; ib < n_blk; ib += gridDim.x) {
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n
             s_nsel = 0;
         int32_t *keys, *cnts;
         const uint32_t cap = census_block(r0, r1, e0, e1, rowptr, colind, val, s_keys, s_cnts,
-                                          gkeys, gcnts, &keys, &cnts);
+                                          SLOTS, gkeys, gcnts, &keys, &cnts);
 
         for (uint32_t s = threadIdx.x; s < cap; s += CV_WG) {
             const int32_t key = keys[s];
@@ -499,6 +506,26 @@ void free_matrix(BdcMatrix &m)
     m.rem_mask = nullptr;
 }
 
+// Census launch with the smallest LDS table that holds a block of hmax
+// entries (more entries than 8191 go to the global table).
+void launch_census(int64_t grid, int64_t hmax, int mode, int32_t n, int32_t n_b, int64_t n_blk,
+                   const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                   int32_t *Kb, int32_t *sel_tmp, int32_t *list_tmp, int32_t *gkeys,
+                   int32_t *gcnts, int32_t *hdc_count)
+{
+    const unsigned g = grid_for(grid, 1, 1 << 20);
+    if (hmax < 256)
+        k_census<512><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val, theta, Kb,
+                                            sel_tmp, list_tmp, gkeys, gcnts, hdc_count);
+    else if (hmax < 1024)
+        k_census<2048><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val, theta, Kb,
+                                             sel_tmp, list_tmp, gkeys, gcnts, hdc_count);
+    else
+        k_census<CENSUS_LDS_SLOTS><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val,
+                                                         theta, Kb, sel_tmp, list_tmp, gkeys,
+                                                         gcnts, hdc_count);
+}
+
 int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const double *val)
 {
     const int32_t n = m.n;
@@ -555,9 +582,8 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
                 return rc;
             tmp.add(gcnts);
         }
-        k_census<<<grid_for(n_blk, 1, 1 << 20), CV_WG, 0, 0>>>(
-            0, n, n_b, n_blk, rowptr, colind, val, m.theta, Kb, sel_tmp, list_tmp, gkeys, gcnts,
-            nullptr);
+        launch_census(n_blk, hmax, 0, n, n_b, n_blk, rowptr, colind, val, m.theta, Kb, sel_tmp,
+                      list_tmp, gkeys, gcnts, nullptr);
         if ((rc = launch_ok("census")))
             return rc;
         if ((rc = exclusive_scan_i32(Kb, m.dia_ptr, n_blk, &K, 0)))
@@ -597,9 +623,8 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
                 return rc;
             tmp.add(gcnts);
         }
-        k_census<<<grid_for(n_chunk, 1, 1 << 20), CV_WG, 0, 0>>>(
-            1, n, HDC_CENSUS_ROWS, n_chunk, rowptr, colind, val, m.theta, nullptr, nullptr,
-            nullptr, gkeys, gcnts, gcount);
+        launch_census(n_chunk, hmax, 1, n, HDC_CENSUS_ROWS, n_chunk, rowptr, colind, val, m.theta,
+                      nullptr, nullptr, nullptr, gkeys, gcnts, gcount);
         if ((rc = launch_ok("hdc census")))
             return rc;
         if ((rc = dmalloc((void **)&flag, sizeof(int32_t) * (size_t)span, "offset flags")))

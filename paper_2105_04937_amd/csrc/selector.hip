@@ -70,7 +70,8 @@ __global__ __launch_bounds__(CENSUS_WG) void k_feat_census(
         const int64_t r0 = ib * PROBE_NB, r1 = min((int64_t)n, r0 + PROBE_NB);
         int32_t *keys, *cnts;
         const uint32_t cap = census_block(r0, r1, rowptr[r0], rowptr[r1], rowptr, colind, val,
-                                          s_keys, s_cnts, gkeys, gcnts, &keys, &cnts);
+                                          s_keys, s_cnts, CENSUS_LDS_SLOTS, gkeys, gcnts,
+                                          &keys, &cnts);
         const int base = ib == n_blk - 1 ? N_BINS : 0;
         for (uint32_t s = threadIdx.x; s < cap; s += CENSUS_WG) {
             const int32_t key = keys[s];

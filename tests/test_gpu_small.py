@@ -407,6 +407,26 @@ def test_conversion_and_spmv_are_deterministic():
         assert_same_bits(ys[1], ys[0], "HDC/CSR product")
 
 
+def test_census_table_overflow_to_global():
+    """Blocks whose distinct offsets do not fit the 8192-slot LDS table
+    (4096-row blocks of a matrix with 40 random columns per row; HDC chunks
+    of 10k entries) are counted again in their global table region: the
+    arrays still equal the oracle's byte for byte, and so do blocks of the
+    same matrix that fit (n_b = 64)."""
+    m = synth.random_csr(20000, 77, density=0.002, bands=[0, 1, -1])
+    say("case: census overflow n=%d nnz=%d" % (m.n, m.nnz))
+    rp, ci, v = dev(m)
+    for nb, th in ((4096, 0.005), (64, 0.05)):
+        h = mhdc.MHDCMatrix.from_csr(rp, ci, v, nb, th)
+        check_mhdc_arrays(h, oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, nb, th))
+        h.close()
+    hd = mhdc.HDCMatrix.from_csr(rp, ci, v, 0.01)
+    check_hdc_arrays(hd, oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.01))
+    x = synth.vector(m.n, 4)
+    assert_spmv_close(hd.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), m, x)
+    hd.close()
+
+
 def test_allocation_failure_leaks_nothing():
     """Fail the k-th device allocation of a conversion for every k: each
     attempt reports MHDC_ERR_OOM and returns all memory it took."""
