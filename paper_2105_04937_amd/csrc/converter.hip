@@ -3,8 +3,8 @@
 // Steps (M-HDC, Sec. 4.3; HDC, Sec. 3.4), each a HIP kernel:
 //   1. validate the CSR arrays (one lane per row, error bits in a flag);
 //   2. census: for each row block count the nonzeros of every offset
-//      d = j - i in an open-addressing hash table (in LDS, 512, 2048 or
-//      8192 slots, the smallest that holds the largest block, when the
+//      d = j - i in an open-addressing hash table (in LDS, 512 to 8192
+//      slots, the smallest that holds the largest block, when the
 //      block holds fewer entries than that, else a per-block region of a
 //      global table); only integer atomics on counts, so the counted set
 //      does not depend on the order of the atomics;
@@ -82,8 +82,8 @@ __global__ __launch_bounds__(CV_WG) void k_block_max(int32_t n, int32_t n_b, int
 //   Kb[ib] = number kept, sel_tmp[e0 .. e0+Kb) = kept offsets ascending,
 //   with e0 = rowptr[ib*n_b] (a block keeps at most its entry count).
 // mode 1 (HDC census): add each block's counts into hdc_count[d + n - 1].
-// SLOTS: LDS hash-table slots, the smallest of 512 / 2048 / 8192 that holds
-// the largest block (small tables leave LDS for more resident workgroups:
+// SLOTS: LDS hash-table slots, the smallest of 512 / 2048 / 4096 / 8192 that
+// holds the largest block (small tables leave LDS for more resident workgroups:
 // with 8192 slots only two fit per CU).
 template <int SLOTS>
 __global__ __launch_bounds__(CV_WG) void k_census(int mode, int32_t n, int32_t n_b, int64_t n_blk,
@@ -519,6 +519,9 @@ void launch_census(int64_t grid, int64_t hmax, int mode, int32_t n, int32_t n_b,
                                             sel_tmp, list_tmp, gkeys, gcnts, hdc_count);
     else if (hmax < 1024)
         k_census<2048><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val, theta, Kb,
+                                             sel_tmp, list_tmp, gkeys, gcnts, hdc_count);
+    else if (hmax < 2048)
+        k_census<4096><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val, theta, Kb,
                                              sel_tmp, list_tmp, gkeys, gcnts, hdc_count);
     else
         k_census<CENSUS_LDS_SLOTS><<<g, CV_WG, 0, 0>>>(mode, n, n_b, n_blk, rowptr, colind, val,
