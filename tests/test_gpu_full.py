@@ -26,10 +26,15 @@ class Case:
 
     def check(self, mat, shapes=((2, 256, 1),), want=None):
         """Within 1e-13 |A||x| of the CSR definition; bit-identical to the
-        oracle's sequential kernel `want` (CSR: the oracle's CSR product)."""
+        oracle's sequential kernel `want` (CSR: the oracle's CSR product).
+        The handle's own default launch (the shape the benchmark times) is
+        checked first, then `shapes`."""
         if want is None and isinstance(mat, mhdc.CSRMatrix):
             want = self.yref
-        for shp in shapes:
+        inf = mat.info()
+        default = tuple(inf[f] for f in ("rows_per_lane", "wg_size", "xcd_remap", "csr_mode",
+                                         "rhs_group"))
+        for shp in (default,) + tuple(shapes):
             mat.set_launch(*shp)
             y = mat.spmv(self.xd)
             assert_spmv_close(y, self.m, self.x, Y_ref=self.yref, absAx=self.scale)
@@ -131,3 +136,24 @@ def test_partial192_hdc_csr(partial192):
     check_hdc_arrays(hd, rh)
     c.check(hd, want=oracle.hdc_spmv(rh, c.x))
     c.check(mhdc.CSRMatrix.from_csr(*c.d), shapes=((2, 256, 1), (1, 64, 1)))
+
+
+def test_hepta256_spmm16(hepta256):
+    """16 right-hand sides on the 256^3 matrix in the default launch: every
+    column equals that column's own SpMV bit for bit (itself pinned to the
+    oracle above), and column 0 the oracle's Fig. 16 kernel."""
+    c, m = hepta256, hepta256.m
+    say("case: heptadiagonal 256^3 spmm k=16")
+    h = mhdc.MHDCMatrix.from_csr(*c.d, 256, 0.6)
+    k = 16
+    X = torch.empty((k, m.n), dtype=torch.float64, device="cuda")
+    X[0] = c.xd
+    for r in range(1, k):
+        X[r] = torch.from_numpy(synth.vector(m.n, 100 + r)).cuda()
+    Y = h.spmm(X)
+    for r in range(k):
+        y1 = h.spmv(X[r].contiguous())
+        assert torch.equal(Y[r].view(torch.int64), y1.view(torch.int64)), "column %d" % r
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6)
+    assert_oracle_bits(Y[0], oracle.mhdc_spmv(ref, c.x), "spmm column 0")
+    h.close()
