@@ -427,6 +427,28 @@ def test_census_table_overflow_to_global():
     hd.close()
 
 
+def test_concurrent_streams_share_a_handle():
+    """A handle is read-only after conversion: products on two streams at
+    once (default priority, different x and y) give the bits of the same
+    products run one after the other."""
+    m = synth.partially_diagonal(20, 6, drop=synth.OCTANT_DROP)
+    rp, ci, v = dev(m)
+    say("case: two streams, one handle n=%d" % m.n)
+    h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 64, 0.6)
+    xs = [torch.from_numpy(synth.vector(m.n, 30 + i)).cuda() for i in range(2)]
+    want = [h.spmv(x).cpu().numpy() for x in xs]
+    ys = [torch.empty(m.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for _ in range(20):
+        for x, y, st in zip(xs, ys, streams):
+            h.spmv(x, y, stream=st)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert_same_bits(ys[i].cpu().numpy(), want[i], "stream %d" % i)
+    h.close()
+
+
 def test_allocation_failure_leaks_nothing():
     """Fail the k-th device allocation of a conversion for every k: each
     attempt reports MHDC_ERR_OOM and returns all memory it took."""
