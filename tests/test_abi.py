@@ -46,3 +46,48 @@ def test_error_strings_without_gpu():
     L = mhdc.lib()
     assert L.mhdc_error_string(-2) == b"MHDC_ERR_BAD_CSR"
     assert L.mhdc_last_error() == 0
+
+
+def header_structs():
+    """{typedef name: [(field, C type), ...]} of the plain structs the
+    header declares (comments stripped, 'int32_t a, b;' expanded)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+)\s*;", src, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            ctype, names = decl.split(None, 1)
+            fields += [(f.strip(), ctype) for f in names.split(",")]
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_header():
+    """The ctypes structures of the binding have the header's fields, in
+    its order and with the same types, so no layout can drift apart."""
+    from paper_2105_04937_amd import mhdc
+    ctypes_of = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64,
+                 "double": ctypes.c_double, "float": ctypes.c_float,
+                 "mhdc_launch": mhdc.Launch}
+    pairs = {"mhdc_info": mhdc.Info, "mhdc_launch": mhdc.Launch,
+             "mhdc_batch_info": mhdc.BatchInfo, "mhdc_tune_result": mhdc.TuneResult,
+             "mhdc_select_result": mhdc.SelectResult}
+    structs = header_structs()
+    assert set(pairs) <= set(structs), sorted(structs)
+    for cname, py in pairs.items():
+        want = [(f, ctypes_of[t]) for f, t in structs[cname]]
+        assert list(py._fields_) == want, cname
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it says so and exits
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
