@@ -2,8 +2,9 @@
 matrices (200 of grid side 48..144, 40 of side 145..208): each matrix is
 regenerated from its stored seed and family, the selector (mhdc_select
 with the committed network and the byte-model judge) picks (theta, n_b),
-and three handles are timed back to back in
-interleaved rounds with mhdc_time_spmv: the selection, the policy
+mhdc_select_refine times that choice against its grid neighbours and the
+policy, and four handles are timed back to back in interleaved rounds with
+mhdc_time_spmv: the selection, the refined selection, the policy
 (theta = 0.6, n_b = 256; Sec. 6.4.3) and the grid point that was fastest in
 the stored exhaustive sweep.  Re-timing the stored best removes the bias of
 taking a minimum over 40 noisy timings.
@@ -53,9 +54,11 @@ def main():
         x = torch.rand(n, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
         y = torch.empty_like(x)
         h_sel, dec = mhdc.select(rp, ci, v, model=net, tolerance=learned.JUDGE_TOLERANCE)
+        h_ref, dec_ref = mhdc.select_refine(rp, ci, v, model=net,
+                                            tolerance=learned.JUDGE_TOLERANCE)
         best_key = min(r["us"], key=r["us"].get)
         bth, bnb = best_key.split("/")
-        hs = {"selected": h_sel,
+        hs = {"selected": h_sel, "refined": h_ref,
               "policy": mhdc.MHDCMatrix.from_csr(rp, ci, v, learned.RULE[1], learned.RULE[0]),
               "best": mhdc.MHDCMatrix.from_csr(rp, ci, v, int(bnb), float(bth))}
         t = {k: float("inf") for k in hs}
@@ -65,16 +68,21 @@ def main():
         for h in hs.values():
             h.close()
         rows.append(dict(id=r["id"], n=n, selected=learned.key(dec["theta"], dec["n_b"]),
+                         refined=learned.key(dec_ref["theta"], dec_ref["n_b"]),
+                         t_refined=round(t["refined"], 3),
                          best=best_key, used_rule=bool(dec["used_rule"]),
                          t_selected=round(t["selected"], 3), t_policy=round(t["policy"], 3),
                          t_best=round(t["best"], 3)))
         del rp, ci, v, x, y
     ts = np.array([q["t_selected"] for q in rows])
+    tr = np.array([q["t_refined"] for q in rows])
     tp = np.array([q["t_policy"] for q in rows])
     tb = np.array([q["t_best"] for q in rows])
     rep = dict(matrices=len(rows), rounds=args.rounds,
                mean_selected_over_best=round(float(np.mean(ts / tb)), 4),
                within_5pct_selected=round(float(np.mean(ts <= 1.05 * tb)), 3),
+               mean_refined_over_best=round(float(np.mean(tr / tb)), 4),
+               within_5pct_refined=round(float(np.mean(tr <= 1.05 * tb)), 3),
                mean_policy_over_best=round(float(np.mean(tp / tb)), 4),
                within_5pct_policy=round(float(np.mean(tp <= 1.05 * tb)), 3),
                geomean_speedup_over_policy=round(float(np.exp(np.mean(np.log(tp / ts)))), 4),

@@ -356,6 +356,19 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr,
                         mhdc_mlp model, double tolerance,
                         mhdc_select_result *out);
 
+/* mhdc_select's choice refined by measurement (the paper leaves the
+ * choice open, Sec. 7; its sweep grid is that of Sec. 6.4.1): the choice,
+ * its grid neighbours (n_b halved and doubled within [32, 4096], theta
+ * -+ 0.1 within [0.5, 0.9]), the policy (0.6, 256) and the choice's theta
+ * with n_b = 4096 are converted and timed with mhdc_time_spmv on `stream`
+ * (internal x and y), and the fastest handle is returned; out->theta /
+ * n_b / used_rule describe it, the other fields are mhdc_select's.  Up to
+ * seven conversions.  Synchronous; NULL on error (nothing leaks). */
+mhdc_handle mhdc_select_refine(int32_t n, const int32_t *rowptr,
+                               const int32_t *colind, const double *val,
+                               mhdc_mlp model, double tolerance,
+                               hipStream_t stream, mhdc_select_result *out);
+
 /* ------------------------------------------------------ failure injection */
 /* Test hook: the countdown-th device allocation made by the library from now
  * on fails with MHDC_ERR_OOM (0 disables).  Lets a host-side test drive every

@@ -220,6 +220,14 @@ __global__ void k_steps_inc(int32_t *step, int32_t *local_step)
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
+// x = 0.5 (timing input of the refinement; the values do not change the
+// kernel's work)
+__global__ __launch_bounds__(TW) void k_fill_half(double *x, int32_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * TW + threadIdx.x; i < n; i += (int64_t)gridDim.x * TW)
+        x[i] = 0.5;
+}
+
 // bad = 1 if an entry of order[0..count) is outside [0, N)
 __global__ __launch_bounds__(TW) void k_check_order(const int32_t *__restrict__ order, int64_t count,
                                                     int32_t N, int32_t *bad)
@@ -645,6 +653,91 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
     if (out)
         *out = res;
     return pick;
+}
+
+mhdc_handle mhdc_select_refine(int32_t n, const int32_t *rowptr, const int32_t *colind,
+                               const double *val, mhdc_mlp model, double tolerance,
+                               hipStream_t stream, mhdc_select_result *out)
+{
+    clear_error();
+    mhdc_select_result res{};
+    mhdc_handle best = mhdc_select(n, rowptr, colind, val, model, tolerance, &res);
+    if (!best)
+        return nullptr;
+    if (n < 1) {
+        if (out)
+            *out = res;
+        return best;
+    }
+    // the decision's neighbours on the grid of Sec. 6.4.1 (theta in 0.1
+    // steps within [0.5, 0.9], n_b a power of two in [32, 4096]), the
+    // policy and the largest block size
+    struct Cand {
+        double theta;
+        int32_t n_b;
+    };
+    std::vector<Cand> cand;
+    auto add = [&](double th, int32_t nb) {
+        th = std::round(th * 10.0) / 10.0;
+        if (th < 0.5 - 1e-9 || th > 0.9 + 1e-9 || nb < 32 || nb > 4096)
+            return;
+        if (std::fabs(th - res.theta) < 1e-9 && nb == res.n_b)
+            return;
+        for (const Cand &c : cand)
+            if (std::fabs(c.theta - th) < 1e-9 && c.n_b == nb)
+                return;
+        cand.push_back({th, nb});
+    };
+    add(res.theta, res.n_b / 2);
+    add(res.theta, res.n_b * 2);
+    add(res.theta - 0.1, res.n_b);
+    add(res.theta + 0.1, res.n_b);
+    add(0.6, 256);
+    // the largest block of the grid: on matrices of a few 1e5 rows (10-30 us
+    // products) the fewest, longest segments often win by 5-20 %, far from
+    // the network's choice
+    add(res.theta, 4096);
+    double *x = nullptr, *y = nullptr;
+    int rc = dmalloc((void **)&x, sizeof(double) * (size_t)n, "refine x");
+    if (!rc)
+        rc = dmalloc((void **)&y, sizeof(double) * (size_t)n, "refine y");
+    if (!rc) {
+        k_fill_half<<<blocks_for(n < (1 << 22) ? n : (1 << 22)), TW, 0, stream>>>(x, n);
+        rc = launch_ok("refine fill");
+    }
+    float t_best = 0.0f;
+    if (!rc)
+        rc = mhdc_time_spmv(best, x, y, stream, &t_best);
+    for (size_t c = 0; c < cand.size() && !rc; c++) {
+        mhdc_handle h = mhdc_from_csr(n, rowptr, colind, val, cand[c].n_b, cand[c].theta);
+        if (!h) {
+            rc = mhdc_last_error();
+            break;
+        }
+        float t = 0.0f;
+        rc = mhdc_time_spmv(h, x, y, stream, &t);
+        if (!rc && t < t_best) {
+            mhdc_destroy(best);
+            best = h;
+            t_best = t;
+            res.theta = cand[c].theta;
+            res.n_b = cand[c].n_b;
+            res.used_rule = std::fabs(cand[c].theta - 0.6) < 1e-9 && cand[c].n_b == 256;
+        } else {
+            mhdc_destroy(h);
+        }
+    }
+    dfree(x);
+    dfree(y);
+    if (rc) {
+        const std::string msg = mhdc_last_error_message();
+        mhdc_destroy(best);
+        set_error(rc, "select refine: " + msg);
+        return nullptr;
+    }
+    if (out)
+        *out = res;
+    return best;
 }
 
 }  // extern "C"

@@ -135,6 +135,8 @@ SIGNATURES = {
     "mhdc_mlp_destroy": (None, [_vp]),
     "mhdc_time_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
     "mhdc_select": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, ctypes.POINTER(SelectResult)]),
+    "mhdc_select_refine": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, _vp,
+                                 ctypes.POINTER(SelectResult)]),
 }
 
 
@@ -546,6 +548,18 @@ def select(rowptr, colind, val, model=None, tolerance=0.25):
     res = SelectResult()
     h = lib().mhdc_select(n, rp, ci, v, model._h if model is not None else None,
                           float(tolerance), ctypes.byref(res))
+    if not h:
+        _raise()
+    return MHDCMatrix(h, n), res.as_dict()
+
+
+def select_refine(rowptr, colind, val, model=None, tolerance=0.25, stream=None):
+    """select() followed by timing its choice, the choice's grid neighbours
+    and the policy on the device; returns the fastest (MHDCMatrix, dict)."""
+    n, rp, ci, v = _csr_args(rowptr, colind, val)
+    res = SelectResult()
+    h = lib().mhdc_select_refine(n, rp, ci, v, model._h if model is not None else None,
+                                 float(tolerance), _stream(stream), ctypes.byref(res))
     if not h:
         _raise()
     return MHDCMatrix(h, n), res.as_dict()

@@ -150,3 +150,32 @@ def test_select_policy_network_and_judge():
     p[-2] = np.nan
     h, r = mhdc.select(*d, model=mhdc.MLP(p))
     assert r["net_ok"] == 0 and r["used_rule"] == 1
+
+
+def test_select_refine_returns_a_timed_neighbour():
+    """mhdc_select_refine returns mhdc_select's choice, one of its grid
+    neighbours (n_b halved / doubled, theta -+ 0.1), the policy or the
+    choice's theta at n_b = 4096, and the handle is exactly the oracle's
+    conversion of that (theta, n_b)."""
+    m = synth.partially_diagonal(24, 12)
+    say("case: select refine n=%d" % m.n)
+    d = dev(m)
+    x = synth.vector(m.n, 2)
+    xd = torch.from_numpy(x).cuda()
+    for model in (None, _fixed_net(0.68, 7.2), _fixed_net(0.9, 12.0)):
+        _, r0 = mhdc.select(*d, model=model, tolerance=1e9)
+        h, r = mhdc.select_refine(*d, model=model, tolerance=1e9)
+        allowed = {(round(r0["theta"], 1), r0["n_b"]), (0.6, 256), (round(r0["theta"], 1), 4096)}
+        for th, nb in ((r0["theta"], r0["n_b"] // 2), (r0["theta"], r0["n_b"] * 2),
+                       (r0["theta"] - 0.1, r0["n_b"]), (r0["theta"] + 0.1, r0["n_b"])):
+            th = round(th, 1)
+            if 0.5 <= th <= 0.9 and 32 <= nb <= 4096:
+                allowed.add((th, nb))
+        got = (round(r["theta"], 1), r["n_b"])
+        assert got in allowed, (got, allowed)
+        assert r["used_rule"] == (got == (0.6, 256))
+        inf = h.info()
+        assert (round(inf["theta"], 1), inf["n_b"]) == got
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, got[1], r["theta"])
+        assert_oracle_bits(h.spmv(xd), oracle.mhdc_spmv(ref, x), "refined %s" % (got,))
+        h.close()
