@@ -29,7 +29,14 @@ def test_selector_gain_over_policy():
             rep["matrices"], rep["mean_ratio_selected"], rep["mean_ratio_rule"],
             rep["within_5pct_selected"], rep["within_5pct_rule"],
             rep["geomean_speedup_over_rule"]))
+    say("refined (choice, grid neighbours, policy, n_b = 4096 timed): mean t/t_best %.4f, "
+        "within 5%%: %.3f" % (rep["mean_ratio_refined"], rep["within_5pct_refined"]))
     assert rep["matrices"] == 240
+    # the refinement picks from a superset of the selection
+    assert rep["mean_ratio_refined"] <= rep["mean_ratio_selected"]
+    assert rep["within_5pct_refined"] >= rep["within_5pct_selected"]
+    # and is within 5% of the exhaustive search on nearly every matrix
+    assert rep["within_5pct_refined"] >= 0.95 and rep["mean_ratio_refined"] <= 1.02
     # within 5% of exhaustive search on average, and better than the policy
     assert rep["mean_ratio_selected"] <= 1.05
     assert rep["mean_ratio_selected"] < rep["mean_ratio_rule"]
