@@ -260,6 +260,15 @@ def main():
                                 "gflops": round(2 * m3.nnz / ts / 1e9, 2)}
         log("selected theta=%.1f n_b=%d %8.3f us/step" % (dec["theta"], dec["n_b"], ts * 1e6))
         hsel.close()
+        # the same choice refined by timing its grid neighbours on the device
+        href, dref = mhdc.select_refine(*d3, model=learned.load_network(),
+                                        tolerance=learned.JUDGE_TOLERANCE, stream=stream)
+        tr = time_steps(lambda: href.spmv(x3, ys, stream), args.steps // 2, args.warmup, stream)
+        res["mhdc_refined"] = {"theta": dref["theta"], "n_b": dref["n_b"],
+                               "used_rule": bool(dref["used_rule"]), "us": round(tr * 1e6, 2),
+                               "gflops": round(2 * m3.nnz / tr / 1e9, 2)}
+        log("refined  theta=%.1f n_b=%d %8.3f us/step" % (dref["theta"], dref["n_b"], tr * 1e6))
+        href.close()
         best = min(v_["us"] for k_, v_ in res.items() if k_.startswith("mhdc"))
         res["speedup_best_mhdc_vs_csr"] = round(res["csr"]["us"] / best, 4)
         res["workload"] = "27-point 192^3, octant drops {0,.05,.1,.2,.3,.5,.7,.9}, +2 random/row"
