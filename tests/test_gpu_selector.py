@@ -179,3 +179,17 @@ def test_select_refine_returns_a_timed_neighbour():
         ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, got[1], r["theta"])
         assert_oracle_bits(h.spmv(xd), oracle.mhdc_spmv(ref, x), "refined %s" % (got,))
         h.close()
+
+
+def test_select_refine_tiny_matrices():
+    """One-row and empty-band matrices go through the refinement as well."""
+    for m in (synth.random_csr(1, 3, density=1.0), synth.random_csr(50, 4, density=0.0),
+              synth.random_csr(70, 5, density=0.1, bands=[0, 1])):
+        say("case: select refine n=%d nnz=%d" % (m.n, m.nnz))
+        d = dev(m)
+        h, r = mhdc.select_refine(*d, model=_fixed_net(0.68, 7.2))
+        x = synth.vector(m.n, 3)
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, r["n_b"], r["theta"])
+        assert_oracle_bits(h.spmv(torch.from_numpy(x).cuda()), oracle.mhdc_spmv(ref, x),
+                           "tiny refined")
+        h.close()
