@@ -363,7 +363,8 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr,
  * with n_b = 4096 are converted and timed with mhdc_time_spmv on `stream`
  * (internal x and y), and the fastest handle is returned; out->theta /
  * n_b / used_rule describe it, the other fields are mhdc_select's.  Up to
- * seven conversions.  Synchronous; NULL on error (nothing leaks). */
+ * six conversions beyond mhdc_select's own.  Synchronous; NULL on error
+ * (nothing leaks). */
 mhdc_handle mhdc_select_refine(int32_t n, const int32_t *rowptr,
                                const int32_t *colind, const double *val,
                                mhdc_mlp model, double tolerance,
