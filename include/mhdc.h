@@ -74,10 +74,14 @@ typedef struct hdc_s *hdc_handle;
 typedef struct csr_s *csr_handle;
 
 /* Sizes and model figures of a handle.  bytes_alg is what one spmv must
- * move at the least with this layout (every stored array element read once,
- * x read once, y written once):
- *   8*S + 4*K + 4*(n_blk+1) + 12*R + (R > 0 ? 4*(n+1) : 0) + 16*n
- * (CSR handles: 12*nnz + 4*(n+1) + 16*n).  bytes_paper is the paper's
+ * move at the least with the format's layout (every stored array element
+ * read once, x read once, y written once):
+ *   M-HDC  4*(n_blk+1) + 4*K + 8*S + (R > 0 ? 4*(n+1) : 0) + 12*R + 16*n
+ *   HDC    4*K + 8*S + (R > 0 ? 4*(n+1) : 0) + 12*R + 16*n  (S = K*n; the
+ *          layout of Fig. 7 has no block pointer)
+ *   CSR    4*(n+1) + 12*nnz + 16*n
+ * (the library's remainder bit mask is not counted: the format does not
+ * need it).  bytes_paper is the paper's
  * volume V = V_A + V_x + V_y with v_x = 1 (Eqs. 24/34 of Sec. 5.3):
  *   12*R + 4*n + 8*S + 8*n + 8*n.  alpha and beta are the filling rate and
  * CSR rate of Eqs. 23/33, rp_est the relative performance over CSR of
@@ -133,7 +137,8 @@ typedef struct {
  * diagonal counts (dia_ptr) and per-row remainder counts, and the scatter
  * into segment-local slots dia_val[k*n_b + (i - ib*n_b)].
  * n >= 0; rowptr has n+1 entries; n_b >= 1; 0 <= threshold <= 1.
- * Fails with BAD_CSR on malformed input, SIZE if nnz >= 2^31, OOM if the
+ * Fails with BAD_CSR on malformed input, SIZE if nnz > 2^31 - 4097 (the
+ * kernels number a tile's entries in int32 chunks of up to 2048), OOM if the
  * DIA part (8 * K * n_b bytes) does not fit. */
 mhdc_handle mhdc_from_csr(int32_t n, const int32_t *rowptr,
                           const int32_t *colind, const double *val,
@@ -228,7 +233,17 @@ int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
  * X[count], Y[count]: HOST arrays of DEVICE pointers, column-major blocks
  * with leading dimensions ldx[i], ldy[i] >= n_i (NULL ldx/ldy = n_i).
  * wg_size: 64 or 256 lanes per workgroup (mhdc_batch_tune picks).
- * Y blocks must not overlap any X block. */
+ * Y blocks must not overlap any X block.
+ * One batch runs on one stream at a time: every launch of a batch (run or
+ * graph_launch) takes tiles from the batch's single device counter, so two
+ * launches of the same batch in flight together on different streams race
+ * and give undefined results.  Launches ordered on one stream are safe;
+ * for concurrent streams create one batch per stream (handles may be
+ * shared).  SIZE if the tiles of all items exceed 2^31 - 2^20.
+ *
+ * X/Y are bound at create (and bind) time rather than passed to run: a
+ * captured graph replays the same kernel arguments, and the descriptor
+ * table it reads is the one place the pointers can change between replays. */
 typedef struct mhdc_batch_s *mhdc_batch;
 typedef struct {
     int32_t count, wg_size;
@@ -243,7 +258,8 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats,
                              const int64_t *ldx, double *const *Y,
                              const int64_t *ldy, int32_t wg_size);
 /* Replace the X/Y pointers (synchronous; waits for work in flight).  A
- * captured graph reads the table from device memory and sees the change. */
+ * captured graph reads the table from device memory and sees the change.
+ * On failure the batch keeps its previous binding and stays runnable. */
 int mhdc_batch_bind(mhdc_batch b, const double *const *X, const int64_t *ldx,
                     double *const *Y, const int64_t *ldy);
 /* Enqueue counter reset + persistent kernel on `stream` (asynchronous). */
@@ -252,6 +268,8 @@ int mhdc_batch_run(mhdc_batch b, hipStream_t stream);
  * internal stream, no memset node); every call launches that graph on
  * `stream`.  Asynchronous. */
 int mhdc_batch_graph_launch(mhdc_batch b, hipStream_t stream);
+/* Change the workgroup size (64 or 256; synchronous).  The descriptor table
+ * is rebuilt for the new tile size; on failure nothing changes. */
 int mhdc_batch_set_wg(mhdc_batch b, int32_t wg_size);
 int mhdc_batch_get_info(mhdc_batch b, mhdc_batch_info *out);
 void mhdc_batch_destroy(mhdc_batch b);

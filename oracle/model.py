@@ -83,3 +83,30 @@ def rp_est(alpha, beta, c, vx=1.0):
 def relative_error(rp_estimate, rp_executed):
     """RE = (RP_est - RP_exe) / RP_exe (Sec. 6.4.3)."""
     return (rp_estimate - rp_executed) / rp_executed
+
+
+# -- algorithmic bytes of one product with the stored layouts ---------------
+# The least a product y = A X (k right-hand sides) must move with a given
+# layout: every stored array element read once, every x element read once,
+# every y element written once (the paper's V with v_x = 1, but counting the
+# stored layout exactly: block pointer, offsets, padding slots).  A CSR part
+# with no entries needs no row pointer (nothing of it is read).
+def b_alg_blocked(n, K, S, n_blk, R, k=1):
+    """M-HDC (Sec. 4.3, Fig. 15): dia_ptr[n_blk+1], dia_offset[K],
+    dia_val[S], the remainder's row_ptr[n+1] (if R > 0), col_ind[R], val[R],
+    x and y."""
+    rp = B_INT * (n + 1) if R > 0 else 0.0
+    return (B_INT * (n_blk + 1) + B_INT * K + B_FP * S + rp + (B_INT + B_FP) * R
+            + 2 * B_FP * n * k)
+
+
+def b_alg_hdc(n, K, R, k=1):
+    """HDC (Sec. 3.4, Fig. 7): offset[K], val[K][n], the CSR part's
+    row_ptr[n+1] (if R > 0), col_ind[R], val[R], x and y; no block pointer."""
+    rp = B_INT * (n + 1) if R > 0 else 0.0
+    return B_INT * K + B_FP * K * n + rp + (B_INT + B_FP) * R + 2 * B_FP * n * k
+
+
+def b_alg_csr(n, nnz, k=1):
+    """CSR (Sec. 3.2, Fig. 2): row_ptr[n+1], col_ind[nnz], val[nnz], x, y."""
+    return B_INT * (n + 1) + (B_INT + B_FP) * nnz + 2 * B_FP * n * k

@@ -60,20 +60,12 @@ void fill_info(const BdcMatrix &m, mhdc_info *o)
     o->K = m.K;
     o->S = m.S;
     o->R = m.R;
-    const double n = m.n, nnz = (double)m.nnz, R = (double)m.R, S = (double)m.S,
-                 K = (double)m.K;
+    const double n = m.n, nnz = (double)m.nnz, R = (double)m.R, S = (double)m.S;
     o->beta = nnz > 0 ? R / nnz : 0.0;
     o->alpha = S > 0 ? (nnz - R) / S : 1.0;
-    if (m.kind == KIND_CSR) {
-        o->bytes_alg = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n;
-        o->bytes_paper = 12.0 * nnz + 4.0 * n + 16.0 * n;
-    } else {
-        o->bytes_alg = 8.0 * S + 4.0 * K + 4.0 * ((double)m.n_blk + 1) + 12.0 * R +
-                       (m.R > 0 ? 4.0 * (n + 1) : 0.0) +
-                       (m.rem_mask ? 4.0 * (double)rem_mask_words(m.n) : 0.0) +
-                       16.0 * n;
-        o->bytes_paper = 12.0 * R + 4.0 * n + 8.0 * S + 16.0 * n;
-    }
+    o->bytes_alg = format_bytes(m) + 16.0 * n;
+    o->bytes_paper = m.kind == KIND_CSR ? 12.0 * nnz + 4.0 * n + 16.0 * n
+                                        : 12.0 * R + 4.0 * n + 8.0 * S + 16.0 * n;
     const double v_csr = 12.0 * nnz + 4.0 * n + 16.0 * n;
     o->rp_est = o->bytes_paper > 0 ? v_csr / o->bytes_paper : 1.0;
     o->rows_per_lane = m.launch.rows_per_lane;

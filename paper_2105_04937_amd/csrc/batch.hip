@@ -150,12 +150,18 @@ int batch_grid(int wg, int64_t total_tiles, int32_t *grid)
     return MHDC_OK;
 }
 
-// (Re)build the descriptor table for the current X/Y binding and workgroup
-// size and upload it.
-int upload_items(mhdc_batch_s *b, const double *const *X, const int64_t *ldx, double *const *Y,
-                 const int64_t *ldy)
+// Largest tile count of a batch: the int32 tile counter runs past the last
+// tile by up to one increment per persistent workgroup (at most 256 CUs x 32
+// resident workgroups).
+constexpr int64_t BATCH_MAX_TILES = (int64_t)INT32_MAX - (1LL << 20);
+
+// Build the descriptor table for an X/Y binding and workgroup size, upload
+// it, and only then take it over into the batch: a failure leaves the batch
+// with its previous binding, workgroup size and grid, still runnable.
+int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int64_t *ldx,
+                 double *const *Y, const int64_t *ldy)
 {
-    b->host_items.assign(b->count, BatchItem{});
+    std::vector<BatchItem> items(b->count, BatchItem{});
     int64_t tiles = 0;
     double flops = 0, bytes = 0;
     for (int32_t i = 0; i < b->count; i++) {
@@ -165,32 +171,30 @@ int upload_items(mhdc_batch_s *b, const double *const *X, const int64_t *ldx, do
         int rc = check_operands(m, X[i], lx, Y[i], ly, k);
         if (rc)
             return rc;
-        BatchItem &it = b->host_items[i];
+        BatchItem &it = items[i];
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
         it.kc = kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
         it.rg = row_gather(m.launch.csr_mode, it.kc) ? 1 : 0;
         it.tile_begin = tiles;
-        tiles += ((int64_t)m.n + b->wg - 1) / b->wg;
+        tiles += ((int64_t)m.n + wg - 1) / wg;
         flops += 2.0 * (double)m.nnz * k;
-        const double n = m.n;
-        double a_bytes;
-        if (m.kind == KIND_CSR)
-            a_bytes = 12.0 * (double)m.nnz + 4.0 * (n + 1);
-        else
-            a_bytes = 8.0 * (double)m.S + 4.0 * (double)m.K + 4.0 * ((double)m.n_blk + 1) +
-                      12.0 * (double)m.R +
-                      (m.R > 0 ? 4.0 * (n + 1) : 0.0) +
-                      (m.rem_mask ? 4.0 * (double)rem_mask_words(m.n) : 0.0);
-        bytes += a_bytes + 16.0 * n * k;
+        bytes += format_bytes(m) + 16.0 * (double)m.n * k;
     }
-    if (tiles > INT32_MAX)
+    if (tiles > BATCH_MAX_TILES)
         return set_error(MHDC_ERR_SIZE, "too many tiles in the batch");
+    int32_t grid = 0;
+    int rc = batch_grid(wg, tiles, &grid);
+    if (rc)
+        return rc;
+    MHDC_HIP_CHECK(hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * b->count,
+                             hipMemcpyHostToDevice));
+    b->host_items.swap(items);
+    b->wg = wg;
     b->total_tiles = tiles;
+    b->grid = grid;
     b->flops = flops;
     b->bytes_alg = bytes;
-    MHDC_HIP_CHECK(hipMemcpy(b->d_items, b->host_items.data(), sizeof(BatchItem) * b->count,
-                             hipMemcpyHostToDevice));
-    return batch_grid(b->wg, tiles, &b->grid);
+    return MHDC_OK;
 }
 
 int enqueue(mhdc_batch_s *b, hipStream_t s)
@@ -255,7 +259,7 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats, const int32
     if (!rc)
         rc = dmalloc((void **)&b->d_counter, sizeof(int32_t), "batch counter");
     if (!rc)
-        rc = upload_items(b, X, ldx, Y, ldy);
+        rc = upload_items(b, wg_size, X, ldx, Y, ldy);
     if (rc) {
         dfree(b->d_items);
         dfree(b->d_counter);
@@ -273,7 +277,7 @@ int mhdc_batch_bind(mhdc_batch b, const double *const *X, const int64_t *ldx, do
         return set_error(MHDC_ERR_INVALID_ARG, "batch, X and Y must be non-NULL");
     MHDC_HIP_CHECK(hipDeviceSynchronize());  // replays in flight read the table
     const int32_t grid0 = b->grid;
-    int rc = upload_items(b, X, ldx, Y, ldy);
+    int rc = upload_items(b, b->wg, X, ldx, Y, ldy);
     if (!rc && b->grid != grid0)
         drop_graph(b);
     return rc;
@@ -337,9 +341,10 @@ int mhdc_batch_set_wg(mhdc_batch b, int32_t wg_size)
         lx[i] = b->host_items[i].a.ldx;
         ly[i] = b->host_items[i].a.ldy;
     }
-    b->wg = wg_size;
-    drop_graph(b);
-    return upload_items(b, X.data(), lx.data(), Y.data(), ly.data());
+    int rc = upload_items(b, wg_size, X.data(), lx.data(), Y.data(), ly.data());
+    if (!rc)
+        drop_graph(b);
+    return rc;
 }
 
 int mhdc_batch_get_info(mhdc_batch b, mhdc_batch_info *out)

@@ -443,8 +443,8 @@ int validate_csr(int32_t n, const int32_t *rowptr, const int32_t *colind, const 
     if (ends[1] < 0)
         return set_error(MHDC_ERR_BAD_CSR, "rowptr[n] (nnz) is negative");
     const int64_t nnz = ends[1];
-    if (nnz >= (int64_t)INT32_MAX)
-        return set_error(MHDC_ERR_SIZE, "nnz must be < 2^31 - 1");
+    if (nnz > MAX_NNZ)
+        return set_error(MHDC_ERR_SIZE, "nnz must be at most 2^31 - 4097");
     if (nnz > 0 && (!colind || !val))
         return set_error(MHDC_ERR_INVALID_ARG, "colind/val is NULL");
     if (n > 0) {

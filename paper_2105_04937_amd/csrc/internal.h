@@ -44,6 +44,26 @@ struct BdcMatrix {
 // Words of BdcMatrix::rem_mask for n rows (one bit per 64 rows).
 inline int64_t rem_mask_words(int64_t n) { return (n + 2047) / 2048; }
 
+// Largest accepted nnz.  The SpMV kernels walk a tile's CSR entries in
+// chunks of up to 2048 with int32 entry numbers (chunk end = start + chunk),
+// so entry numbers must stay 4096 below INT32_MAX.
+constexpr int64_t MAX_NNZ = (int64_t)INT32_MAX - 4096;
+
+// Bytes of the format's own arrays that one product reads (Figs. 2, 7, 15):
+// block pointer (M-HDC only: the HDC layout of Fig. 7 has none), offsets,
+// DIA slots, and the CSR part (its row pointer only when it has entries).
+// The remainder bit mask is an index of this library, not of the format,
+// and is not counted.  Every term is an integer below 2^53: the sum is exact.
+inline double format_bytes(const BdcMatrix &m)
+{
+    const double n = m.n;
+    if (m.kind == KIND_CSR)
+        return 4.0 * (n + 1) + 12.0 * (double)m.nnz;
+    const double blk_ptr = m.kind == KIND_HDC ? 0.0 : 4.0 * ((double)m.n_blk + 1);
+    return blk_ptr + 4.0 * (double)m.K + 8.0 * (double)m.S + (m.R > 0 ? 4.0 * (n + 1) : 0.0) +
+           12.0 * (double)m.R;
+}
+
 // Thread-local error state.
 int set_error(int code, const std::string &msg);
 void clear_error();

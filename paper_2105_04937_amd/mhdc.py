@@ -417,9 +417,14 @@ class Batch:
         return xp, yp, lx, ly
 
     def bind(self, Xs, Ys):
+        old = self.Xs, self.Ys
         self.Xs, self.Ys = list(Xs), list(Ys)
-        xp, yp, lx, ly = self._ptrs()
-        _check(lib().mhdc_batch_bind(self._h, xp, lx, yp, ly))
+        try:
+            xp, yp, lx, ly = self._ptrs()
+            _check(lib().mhdc_batch_bind(self._h, xp, lx, yp, ly))
+        except Exception:
+            self.Xs, self.Ys = old  # the library keeps its previous binding too
+            raise
 
     def run(self, stream=None):
         _check(lib().mhdc_batch_run(self._h, _stream(stream)))

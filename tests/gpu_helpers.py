@@ -79,3 +79,38 @@ def assert_oracle_bits(y_gpu, y_oracle, name):
     """The GPU kernel reproduces the paper's sequential kernel bit for bit."""
     y = y_gpu.detach().cpu().numpy() if isinstance(y_gpu, torch.Tensor) else y_gpu
     assert_same_bits(y, y_oracle, name)
+
+
+def check_byte_model(mat, m, ref=None):
+    """The byte-model figures a handle reports (mhdc_info) equal the oracle
+    model's (Sec. 5.3, Eqs. 23-36) computed from the oracle converter's own
+    layout `ref` (None for a CSR handle): the integer byte counts and the
+    alpha/beta divisions exactly, rp_est exactly as V_CSR / V and within
+    1e-12 of the closed form of Eq. 28."""
+    from oracle import model
+    inf = mat.info()
+    n, nnz = m.n, m.nnz
+    if ref is None:
+        K, S, R, n_blk = 0, 0, nnz, inf["n_blk"]
+        want_alg = model.b_alg_csr(n, nnz)
+        want_v = model.v_csr_general(n, nnz)
+    else:
+        K, S, R, n_blk = ref.K, ref.dia_val.size, ref.R, ref.n_blk
+        if inf["kind"] == 1:
+            assert S == K * n
+            want_alg = model.b_alg_hdc(n, K, R)
+        else:
+            want_alg = model.b_alg_blocked(n, K, S, n_blk, R)
+        want_v = model.v_hdc_blocked(n, R, S)
+    got = tuple(inf[f] for f in ("nnz", "K", "S", "R", "n_blk"))
+    assert got == (nnz, K, S, R, n_blk), (got, (nnz, K, S, R, n_blk))
+    assert inf["bytes_alg"] == want_alg, (inf["bytes_alg"], want_alg)
+    assert inf["bytes_paper"] == want_v, (inf["bytes_paper"], want_v)
+    alpha, beta = model.alpha_beta(nnz, R, S)
+    assert (inf["alpha"], inf["beta"]) == (alpha, beta)
+    v_csr = model.v_csr_general(n, nnz)
+    assert inf["rp_est"] == (v_csr / want_v if want_v > 0 else 1.0)
+    if n > 0 and nnz > 0:
+        eq28 = model.rp_est(alpha, beta, nnz / n)
+        assert abs(inf["rp_est"] - eq28) <= 1e-12 * eq28, (inf["rp_est"], eq28)
+    return inf

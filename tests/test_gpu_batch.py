@@ -114,6 +114,21 @@ def test_batch_tune_and_errors(batch_case):
     with pytest.raises(mhdc.MhdcError) as e:   # Y_i aliases X_i
         mhdc.Batch(mats, Xs, Ys=Xs)
     assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    # a refused rebinding leaves the batch with its previous binding: it
+    # still runs, and a later workgroup-size change rebuilds from it
+    b = mhdc.Batch(mats, Xs)
+    with pytest.raises(mhdc.MhdcError) as e:
+        b.bind(Xs, Xs)
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    b.run()
+    _check_items(items, mats, Xs, b.Ys, refs)
+    b.set_wg(64)
+    assert b.info()["wg_size"] == 64
+    for Y in b.Ys:
+        Y.fill_(float("nan"))
+    b.run()
+    _check_items(items, mats, Xs, b.Ys, refs)
+    b.close()
 
 
 @pytest.mark.parametrize("k", [1, 4])

@@ -9,8 +9,8 @@ import torch
 
 import oracle
 from paper_2105_04937_amd import mhdc, synth
-from tests.gpu_helpers import (assert_oracle_bits, assert_spmv_close, check_hdc_arrays,
-                               check_mhdc_arrays, check_round_trip, dev, say)
+from tests.gpu_helpers import (assert_oracle_bits, assert_spmv_close, check_byte_model,
+                               check_hdc_arrays, check_mhdc_arrays, check_round_trip, dev, say)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -95,6 +95,7 @@ def test_hepta256_spmv(hepta256, n_b):
     if n_b in (256, 4096):
         ref = oracle.mhdc_from_csr(c.m.rowptr, c.m.colind, c.m.val, n_b, 0.6)
         check_mhdc_arrays(h, ref)
+        check_byte_model(h, c.m, ref)
         check_round_trip(h, c.m)
         want = oracle.mhdc_spmv(ref, c.x)
     c.check(h, shapes=((2, 256, 1), (1, 64, 1), (4, 256, 1)), want=want)
@@ -107,23 +108,30 @@ def test_hepta256_hdc_csr(hepta256):
     assert hd.info()["K"] == 7
     rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
     check_hdc_arrays(hd, rh)
+    check_byte_model(hd, m, rh)
     c.check(hd, want=oracle.hdc_spmv(rh, c.x))
-    c.check(mhdc.CSRMatrix.from_csr(*c.d))
+    cs = mhdc.CSRMatrix.from_csr(*c.d)
+    check_byte_model(cs, m)
+    c.check(cs)
 
 
-@pytest.mark.parametrize("n_b", [32, 96, 128, 256])
-def test_partial192_mhdc(partial192, n_b):
+# (n_b, theta): the policy theta at four block sizes, and the selector's
+# choices the benchmark reports for this matrix (theta 0.5 at n_b 64 / 128)
+@pytest.mark.parametrize("n_b,theta", [(32, 0.6), (96, 0.6), (128, 0.6), (256, 0.6),
+                                       (64, 0.5), (128, 0.5)])
+def test_partial192_mhdc(partial192, n_b, theta):
     c, m = partial192, partial192.m
-    say("case: partially diagonal 192^3 n_b=%d" % n_b)
-    h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, 0.6)
+    say("case: partially diagonal 192^3 n_b=%d theta=%.1f" % (n_b, theta))
+    h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, theta)
     want = None
-    if n_b == 128:
-        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, 0.6)
+    if n_b in (64, 128):
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, theta)
         check_mhdc_arrays(h, ref)
+        check_byte_model(h, m, ref)
         check_round_trip(h, m)
         want = oracle.mhdc_spmv(ref, c.x)
     c.check(h, shapes=((2, 256, 1), (1, 64, 1)), want=want)
-    if n_b == 128:
+    if (n_b, theta) == (128, 0.6):
         inf = h.info()
         assert 0.8 < inf["alpha"] < 0.95 and 0.2 < inf["beta"] < 0.3
 
@@ -134,8 +142,11 @@ def test_partial192_hdc_csr(partial192):
     hd = mhdc.HDCMatrix.from_csr(*c.d, 0.6)
     rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
     check_hdc_arrays(hd, rh)
+    check_byte_model(hd, m, rh)
     c.check(hd, want=oracle.hdc_spmv(rh, c.x))
-    c.check(mhdc.CSRMatrix.from_csr(*c.d), shapes=((2, 256, 1), (1, 64, 1)))
+    cs = mhdc.CSRMatrix.from_csr(*c.d)
+    check_byte_model(cs, m)
+    c.check(cs, shapes=((2, 256, 1), (1, 64, 1)))
 
 
 def test_hepta256_spmm16(hepta256):

@@ -296,6 +296,16 @@ def test_error_paths():
             with pytest.raises(mhdc.MhdcError) as e:
                 make()
             assert e.value.name == "MHDC_ERR_BAD_CSR"
+    # nnz above 2^31 - 4097 is refused from rowptr[n] alone, before any
+    # kernel reads colind or val
+    for make in (lambda p: mhdc.MHDCMatrix.from_csr(p, ci, v, 4, 0.6),
+                 lambda p: mhdc.HDCMatrix.from_csr(p, ci, v, 0.6),
+                 lambda p: mhdc.CSRMatrix.from_csr(p, ci, v)):
+        for last in (2**31 - 4096, 2**31 - 1):
+            pbig = torch.tensor([0, 0, last], dtype=torch.int32, device="cuda")
+            with pytest.raises(mhdc.MhdcError) as e:
+                make(pbig)
+            assert e.value.name == "MHDC_ERR_SIZE"
     h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 4, 0.6)
     buf = torch.zeros(2 * m.n, dtype=torch.float64, device="cuda")
     with pytest.raises(mhdc.MhdcError) as e:

@@ -318,6 +318,57 @@ def test_model_eq28_matches_volumes():
     assert model.rp_est(1.0, 0.0, 1e9) == pytest.approx(1.5, rel=1e-6)
 
 
+def test_b_alg_example_by_hand(example):
+    """Algorithmic bytes of the Example matrix counted by hand from the
+    printed layouts: Fig. 15 (bl = 4, theta = 0.6: dia_ptr 3, offsets 5,
+    20 slots, remainder row_ptr 9, 3 entries), Fig. 7 (theta = 0.6: 2
+    offsets, 16 slots, 7 entries), Fig. 2 (20 entries); x and y 8 each."""
+    n, nnz = example["n"], example["val"].size
+    assert model.b_alg_blocked(n, 5, 20, 2, 3) == 4 * 3 + 4 * 5 + 8 * 20 + 4 * 9 + 12 * 3 + 16 * 8
+    assert model.b_alg_hdc(n, 2, 7) == 4 * 2 + 8 * 16 + 4 * 9 + 12 * 7 + 16 * 8
+    assert model.b_alg_csr(n, nnz) == 4 * 9 + 12 * 20 + 16 * 8
+    # paper volumes (Eqs. 24/34, v_x = 1): no block pointer, no offsets
+    assert model.v_hdc_blocked(n, 3, 20) == 12 * 3 + 4 * 8 + 8 * 20 + 8 * 8 + 8 * 8
+    assert model.v_csr_general(n, nnz) == 12 * 20 + 4 * 8 + 16 * 8
+
+
+@pytest.mark.parametrize("m", _small_cases()[:6], ids=lambda m: "n%d_s%d" % (m.n, m.meta["seed"]))
+@pytest.mark.parametrize("bl", [1, 4, 7, 1000])
+def test_b_alg_is_the_stored_layout(m, bl):
+    """B_alg equals the bytes of the arrays the oracle's converters actually
+    store (a remainder row pointer only when the remainder has entries),
+    plus x read once and y written once, k columns each."""
+    for theta in (0.0, 0.6, 1.0):
+        mh = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, theta)
+        stored = (mh.dia_ptr.nbytes + mh.dia_off.nbytes + mh.dia_val.nbytes + mh.rem_col.nbytes
+                  + mh.rem_val.nbytes + (mh.rem_ptr.nbytes if mh.R > 0 else 0))
+        for k in (1, 3):
+            xy = 2 * 8 * m.n * k
+            assert model.b_alg_blocked(m.n, mh.K, mh.dia_val.size, mh.n_blk, mh.R, k) == stored + xy
+        hd = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, theta)
+        stored = (hd.dia_off.nbytes + hd.dia_val.nbytes + hd.rem_col.nbytes + hd.rem_val.nbytes
+                  + (hd.rem_ptr.nbytes if hd.R > 0 else 0))
+        assert model.b_alg_hdc(m.n, hd.K, hd.R) == stored + 16 * m.n
+    assert model.b_alg_csr(m.n, m.nnz, 2) == (m.rowptr.nbytes + m.colind.nbytes + m.val.nbytes
+                                             + 2 * 8 * m.n * 2)
+
+
+def test_b_alg_heptadiagonal_closed_form():
+    """7-point grid of side N with bl = N (one grid line per block): every
+    block keeps offsets 0 and +-1, and +-N, +-N^2 unless its line lies on
+    the matching face, so K = 3N^2 + 4N(N-1), n_blk = N^2, R = 0 and
+    B_alg = 4(N^2+1) + 4K + 8KN + 16N^3 (1,207,955,460 bytes at N = 256)."""
+    for N in (5, 8, 12):
+        m = synth.heptadiagonal(N, 2)
+        mh = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, N, 0.6)
+        K = 3 * N * N + 4 * N * (N - 1)
+        assert (mh.K, mh.R, mh.n_blk) == (K, 0, N * N)
+        want = 4 * (N * N + 1) + 4 * K + 8 * K * N + 16 * N ** 3
+        assert model.b_alg_blocked(m.n, mh.K, mh.dia_val.size, mh.n_blk, mh.R) == want
+    N, K = 256, 3 * 256 ** 2 + 4 * 256 * 255
+    assert model.b_alg_blocked(N ** 3, K, K * N, N * N, 0) == 1_207_955_460
+
+
 def test_stream_kernels():
     """Sec. 6.2 kernels on integer-valued arrays, where every result is
     exact: C[i] = 1 + i * (3 + i) for the direct kernel; the indirect kernel
