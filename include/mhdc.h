@@ -331,6 +331,18 @@ int mhdc_mlp_get_params(mhdc_mlp m, float *params_host);
 /* out[B][2] = network(X[B][66]); device arrays; asynchronous on stream. */
 int mhdc_mlp_forward(mhdc_mlp m, const float *X, int32_t B, float *out,
                      hipStream_t stream);
+/* The forward pass of mhdc_mlp_forward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels in the same order, so
+ * out holds the same bits, but the two hidden layers live in a fixed 2 MB
+ * device array of the library (one per GPU, kept until the process ends)
+ * and nothing is allocated, freed or synchronised.  1 <= B <= 2048 (SIZE
+ * beyond).  X[B][66] and out[B][2] are caller device arrays.  Calls on one
+ * GPU share that array: two calls that overlap in time on the same GPU
+ * (different streams, or different host threads) race and give undefined
+ * results; order them on one stream.  Asynchronous on stream. */
+int mhdc_mlp_forward_noalloc(mhdc_mlp m, const float *X, int32_t B, float *out,
+                             hipStream_t stream);
 /* loss = sum_r (w0 (o_r0 - T_r0)^2 + w1 (o_r1 - T_r1)^2) / B and its
  * gradient (MHDC_MLP_PARAMS floats, parameter order) by backpropagation;
  * device arrays; asynchronous on stream. */

@@ -27,6 +27,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -274,6 +275,40 @@ __global__ void k_decode(const float *__restrict__ out, int B, double *theta, in
     nb[r] = 1 << (int)l;
 }
 
+// Hidden activations of the forward pass that allocates nothing
+// (mhdc_mlp_forward_noalloc): two layers of at most NOALLOC_MAX_B rows of
+// HID floats, 2 MB in all.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes this name to a kernel (on
+// the host it is a stand-in, not a device address): it looks the address up
+// per device with hipGetSymbolAddress and passes that.
+constexpr int NOALLOC_MAX_B = 2048;
+static __device__ __align__(256) float scratch[2 * NOALLOC_MAX_B * HID];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int noalloc_scratch(float **out)
+{
+    int dev = 0;
+    MHDC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(MHDC_ERR_HIP, std::string("scratch address lookup: ") +
+                                               hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MHDC_OK;
+}
+
 }  // namespace
 }  // namespace mhdc
 
@@ -457,6 +492,28 @@ int mhdc_mlp_forward(mhdc_mlp M, const float *X, int32_t B, float *out, hipStrea
     MHDC_HIP_CHECK(hipMemcpyAsync(out, M->out, sizeof(float) * B * N_OUT,
                                   hipMemcpyDeviceToDevice, stream));
     return launch_ok("mlp forward");
+}
+
+int mhdc_mlp_forward_noalloc(mhdc_mlp M, const float *X, int32_t B, float *out,
+                             hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !out || B < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "network, X, out and B >= 1 required");
+    if (B > NOALLOC_MAX_B)
+        return set_error(MHDC_ERR_SIZE,
+                         "B exceeds 2048 rows, the scratch size of the allocation-free forward pass");
+    float *s = nullptr;
+    int rc = noalloc_scratch(&s);
+    if (rc)
+        return rc;
+    float *h1 = s, *h2 = s + (size_t)NOALLOC_MAX_B * HID;
+    // the kernels and their order are those of mhdc_mlp_forward, so the
+    // outputs are the same bits; the last layer writes `out` directly
+    k_dense_fwd<<<blocks_for(B * HID), TW, 0, stream>>>(X, N_IN, M->p + P_W1, M->p + P_B1, HID, h1, B, 1);
+    k_dense_fwd<<<blocks_for(B * HID), TW, 0, stream>>>(h1, HID, M->p + P_W2, M->p + P_B2, HID, h2, B, 1);
+    k_dense_fwd<<<blocks_for(B * N_OUT), TW, 0, stream>>>(h2, HID, M->p + P_W3, M->p + P_B3, N_OUT, out, B, 0);
+    return launch_ok("mlp forward (no allocation)");
 }
 
 int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, float w0,

@@ -127,6 +127,7 @@ SIGNATURES = {
     "mhdc_mlp_create": (_vp, [_vp]),
     "mhdc_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
     "mhdc_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
+    "mhdc_mlp_forward_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "mhdc_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float,
                                           _vp, _vp, _vp]),
     "mhdc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i64, _i32, ctypes.c_float,
@@ -496,6 +497,16 @@ class MLP:
         out = torch.empty((B, 2), dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_forward(self._h, _dptr(X, torch.float32, "X"), B,
                                       _dptr(out, torch.float32, "out"), _stream(stream)))
+        return out
+
+    def forward_noalloc(self, X, out, stream=None):
+        """mhdc_mlp_forward_noalloc: the forward pass into a caller-provided
+        (B, 2) float32 output, with no device allocation in the library."""
+        B = self._rows(X)
+        if tuple(out.shape) != (B, 2):
+            raise ValueError("out must have shape (B, 2)")
+        _check(lib().mhdc_mlp_forward_noalloc(self._h, _dptr(X, torch.float32, "X"), B,
+                                              _dptr(out, torch.float32, "out"), _stream(stream)))
         return out
 
     def loss_grad(self, X, T, w=(1.0, 1.0), stream=None):
