@@ -1,13 +1,15 @@
 """Multi-right-hand-side products Y = A X (k = 1, 2, 4, 8, 16) on the
 heptadiagonal 7-point 256^3 matrix (M-HDC n_b = 256, theta = 0.6, and CSR)
 and on the partially diagonal 27-point 192^3 matrix (M-HDC n_b = 128, CSR).
-X and Y are column-major (n x k, leading dimension n); A is read once per
-launch, so algorithmic bytes = A + 16 n k.  Each handle runs its default
+X and Y are column-major (n x k, leading dimension n) or, with --layouts
+rowmajor, stored row by row (element (i, r) at X[i*k + r]); A is read once
+per launch, so algorithmic bytes = A + 16 n k.  Each handle runs its default
 launch shape; a step is one spmm with inputs resident in HBM, timed with
 HIP events on the launch stream.
 
     python bench_spmm.py [--steps K] [--warmup W] [--matrix all|hepta|partial]
                          [--ks 1,2,4,8,16] [--formats mhdc,csr]
+                         [--layouts colmajor,rowmajor]
 
 Prints one JSON line; value = GFLOP/s of M-HDC at k = 16 on the 256^3 case.
 """
@@ -47,9 +49,12 @@ def main():
     ap.add_argument("--matrix", choices=("all", "hepta", "partial"), default="all")
     ap.add_argument("--ks", default="1,2,4,8,16", help="right-hand side counts, comma-separated")
     ap.add_argument("--formats", default="mhdc,csr", help="subset of mhdc,csr")
+    ap.add_argument("--layouts", default="colmajor,rowmajor",
+                    help="subset of colmajor,rowmajor")
     args = ap.parse_args()
     ks = [int(t) for t in args.ks.split(",")]
     formats = args.formats.split(",")
+    layouts = args.layouts.split(",")
 
     import torch
 
@@ -76,21 +81,28 @@ def main():
             inf = h.info()
             a_bytes = inf["bytes_alg"] - 16.0 * n
             for k in ks:
-                X = torch.rand((k, n), dtype=torch.float64, device=dev, generator=None)
-                Y = torch.empty_like(X)
-                t = timed(lambda: h.spmm(X, Y, s), args.steps, args.warmup, s)
-                gbs = (a_bytes + 16.0 * n * k) / t / 1e9
-                gfl = 2.0 * m.nnz * k / t / 1e9
-                log("%-34s %-12s k=%2d %9.1f us %7.1f GB/s %7.1f GFLOP/s" % (
-                    name, label, k, t * 1e6, gbs, gfl))
-                rows.append(dict(matrix=name, format=label, k=k, us=round(t * 1e6, 2),
-                                 gb_per_s=round(gbs, 1), gflops=round(gfl, 1),
-                                 bytes_alg=a_bytes + 16.0 * n * k))
-                del X, Y
+                for lay in layouts:
+                    if lay == "rowmajor":
+                        X = torch.rand((n, k), dtype=torch.float64, device=dev)
+                        fn = lambda: h.spmm_rowmajor(X, Y, s)  # noqa: E731
+                    else:
+                        X = torch.rand((k, n), dtype=torch.float64, device=dev)
+                        fn = lambda: h.spmm(X, Y, s)  # noqa: E731
+                    Y = torch.empty_like(X)
+                    t = timed(fn, args.steps, args.warmup, s)
+                    gbs = (a_bytes + 16.0 * n * k) / t / 1e9
+                    gfl = 2.0 * m.nnz * k / t / 1e9
+                    log("%-34s %-12s %-8s k=%2d %9.1f us %7.1f GB/s %7.1f GFLOP/s" % (
+                        name, label, lay, k, t * 1e6, gbs, gfl))
+                    rows.append(dict(matrix=name, format=label, layout=lay, k=k,
+                                     us=round(t * 1e6, 2), gb_per_s=round(gbs, 1),
+                                     gflops=round(gfl, 1), bytes_alg=a_bytes + 16.0 * n * k))
+                    del X, Y
             h.close()
         del d, m
         torch.cuda.empty_cache()
-    top = ([r for r in rows if r["k"] == max(ks) and r["format"].startswith("M-HDC")] or rows)[0]
+    top = ([r for r in rows if r["k"] == max(ks) and r["format"].startswith("M-HDC")
+            and r["layout"] == layouts[-1]] or rows)[0]
     print(json.dumps({"metric": "multi-RHS M-HDC SpMM GFLOP/s, FP64, 1xMI355X",
                       "value": top["gflops"], "unit": "GFLOP/s", "higher_is_better": True,
                       "dtype": "f64", "data": "synthetic (seeded stencil matrices, X ~ U[0,1))",

@@ -154,6 +154,14 @@ int mhdc_spmv(mhdc_handle h, const double *x, double *y, hipStream_t stream);
 int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
               int64_t ldy, int32_t k, hipStream_t stream);
 
+/* Y = A X for 1 <= k <= 16 right-hand sides stored row by row: element
+ * (i, r) of X at X[i*ldx + r] (ldx >= k), likewise Y with ldy >= k.  Same
+ * bits in every column as mhdc_spmm.  Each remainder entry reads one row of
+ * X (k contiguous doubles) and each diagonal a contiguous span of rows,
+ * where column-major X costs one cache line per column.  Asynchronous. */
+int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y,
+                       int64_t ldy, int32_t k, hipStream_t stream);
+
 /* Decode back to CSR on the device: rowptr[n+1], colind[nnz], val[nnz]
  * (nnz from mhdc_get_info).  Row i merges, by column, its remainder entries
  * and the nonzero slots of its block's partial diagonals; for canonical CSR
@@ -190,6 +198,9 @@ int hdc_spmv_unblocked(hdc_handle h, const double *x, double *y,
                        hipStream_t stream);
 int hdc_spmm(hdc_handle h, const double *X, int64_t ldx, double *Y,
              int64_t ldy, int32_t k, hipStream_t stream);
+/* Row-major right-hand sides as in mhdc_spmm_rowmajor. */
+int hdc_spmm_rowmajor(hdc_handle h, const double *X, int64_t ldx, double *Y,
+                      int64_t ldy, int32_t k, hipStream_t stream);
 int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val,
                int32_t *rem_ptr, int32_t *rem_col, double *rem_val);
 int hdc_get_info(hdc_handle h, mhdc_info *out);
@@ -204,6 +215,9 @@ csr_handle csr_from_csr(int32_t n, const int32_t *rowptr,
 int csr_spmv(csr_handle h, const double *x, double *y, hipStream_t stream);
 int csr_spmm(csr_handle h, const double *X, int64_t ldx, double *Y,
              int64_t ldy, int32_t k, hipStream_t stream);
+/* Row-major right-hand sides as in mhdc_spmm_rowmajor. */
+int csr_spmm_rowmajor(csr_handle h, const double *X, int64_t ldx, double *Y,
+                      int64_t ldy, int32_t k, hipStream_t stream);
 int csr_get_info(csr_handle h, mhdc_info *out);
 int csr_set_launch(csr_handle h, const mhdc_launch *cfg);
 void csr_destroy(csr_handle h);

@@ -237,6 +237,15 @@ int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ld
     return launch_spmv(h->m, X, ldx, Y, ldy, k, stream);
 }
 
+int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                       int32_t k, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
+}
+
 int mhdc_to_csr(mhdc_handle h, int32_t *rowptr, int32_t *colind, double *val)
 {
     clear_error();
@@ -321,6 +330,15 @@ int hdc_spmm(hdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy,
     return launch_spmv(h->m, X, ldx, Y, ldy, k, stream);
 }
 
+int hdc_spmm_rowmajor(hdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                       int32_t k, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
+}
+
 int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val, int32_t *rem_ptr,
                int32_t *rem_col, double *rem_val)
 {
@@ -393,6 +411,15 @@ int csr_spmm(csr_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy,
     if (!h)
         return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
     return launch_spmv(h->m, X, ldx, Y, ldy, k, stream);
+}
+
+int csr_spmm_rowmajor(csr_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                       int32_t k, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
 }
 
 int csr_get_info(csr_handle h, mhdc_info *out)

@@ -106,6 +106,12 @@ int launch_rem_part(const BdcMatrix &m, const double *x, double *y, hipStream_t 
 int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y,
                 int64_t ldy, int32_t k, hipStream_t stream);
 int check_launch(const mhdc_launch &cfg);
+// Row-major right-hand sides (element (i, r) at X[i*ldx + r], ldx >= k).
+int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
+                      int64_t ldy, int32_t k);
+int rm_columns(int32_t k);  // accumulator width of the row-major kernel (2..16)
+int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                   int32_t k, hipStream_t stream);
 
 // scan.hip: exclusive prefix sum of cnt[0..N) into out[0..N] (out[N] =
 // total), all int32 on the device; total also returned on the host.

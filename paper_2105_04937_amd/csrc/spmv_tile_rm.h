@@ -1,0 +1,186 @@
+// spmv_tile_rm.h -- one row tile of the fused SpMV for 2 to 16 right-hand
+// sides stored row by row (element (i, r) of X at X[i*ldx + r], ldx >= k),
+// shared by the single-matrix launcher (spmv.hip) and the batched kernel
+// (batch.hip).
+//
+// The arithmetic and its order are those of spmv_tile.h: per row and
+// column, the remainder entries in column order, then the block's diagonals
+// in ascending order, every product rounded before it is added -- so every
+// column equals the column-major kernel's bits and the sequential kernels'
+// (Figs. 3, 8, 16).
+//
+// Work mapping (64-lane wavefronts): a wavefront owns 64 consecutive rows.
+// Its lanes are split into RPI = 64/KC row slots times KC columns: lane
+// (s, c) = (lane / KC, lane % KC) accumulates column c of the rows
+// wave_base + s + RPI*q, q < KC.  One load of X then covers RPI consecutive
+// rows times KC columns -- 64 consecutive doubles when ldx = KC -- for a
+// diagonal, and a remainder entry brings its column's row of X (KC
+// doubles, one cache line at KC = 16) instead of KC lines of KC separate
+// column vectors.
+//   * DIA part: each lane loads the value of row wave_base + lane (one
+//     coalesced load per diagonal, non-temporal) and the lanes of row slot s
+//     read the value of their row q from lane s + RPI*q (cross-lane read).
+//   * CSR part: per chunk of the tile's entries, the wavefronts form the
+//     rounded products w * X[col*ldx + c] with lane (s, c) taking entries
+//     s, s + RPI, ... of its wavefront's share (independent gathers, RPI
+//     entries times KC columns per load) and store them in LDS; each lane
+//     then adds the products of its rows' entries in column order.
+#pragma once
+
+#include "spmv_tile.h"
+
+namespace mhdc {
+
+template <int WG, int KC>
+struct TileShapeRm {
+    static_assert(KC >= 2 && KC <= 16 && (KC & (KC - 1)) == 0, "2..16 columns");
+    static constexpr int RPI = 64 / KC;
+    // remainder entries per chunk: 32 KB of products
+    static constexpr int CH = 4096 / KC;
+    static constexpr int LDS_BYTES = CH * KC * 8;
+    static_assert(CH % (WG / 64 * RPI) == 0, "chunk splits evenly over the slots");
+    // products per lane and chunk
+    static constexpr int PER_LANE = CH / (WG / 64) / RPI;
+    // diagonals in flight
+    static constexpr int U = KC >= 8 ? 1 : 2;
+};
+
+template <int WG, int KC, bool HAS_DIA, bool HAS_REM>
+__device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
+{
+    // products are rounded before they are added: no multiply-add fusion
+#pragma clang fp contract(off)
+    using Sh = TileShapeRm<WG, KC>;
+    constexpr int RPI = Sh::RPI;
+    constexpr int CH = Sh::CH;
+    constexpr int U = Sh::U;
+    const int n = a.n;
+    const int64_t tile_base = tile * WG;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wave_base = tile_base + (int64_t)wave * 64;
+    const int s = lane / KC, c = lane % KC;
+    const bool col_live = c < a.k;
+    const double *__restrict__ X = a.X;
+    const int64_t ldx = a.ldx;
+
+    double acc[KC];
+#pragma unroll
+    for (int q = 0; q < KC; q++)
+        acc[q] = 0.0;
+
+    static_assert(WG % 64 == 0 && 32 % (WG / 64) == 0, "tile must cover 64-row groups of one word");
+    bool tile_rem = HAS_REM && a.has_rem;
+    if (tile_rem && a.rem_mask) {
+        const int64_t g0 = tile_base >> 6;
+        const uint32_t word = uniform_load(a.rem_mask, g0 >> 5);
+        tile_rem = ((word >> (g0 & 31)) & ((1u << (WG / 64)) - 1u)) != 0;
+    }
+    if (tile_rem) {
+        const int64_t tile_end = tile_base + WG < n ? tile_base + WG : n;
+        const int32_t e_beg = uniform_load(a.rem_ptr, tile_base);
+        const int32_t e_end = uniform_load(a.rem_ptr, tile_end);
+        if (e_beg < e_end) {
+            double *s_prod = static_cast<double *>(lds);
+            for (int32_t cb = e_beg; cb < e_end; cb += CH) {
+                const int32_t ce = cb + CH < e_end ? cb + CH : e_end;
+                // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W)
+                const int32_t wb = cb + wave * (CH / (WG / 64));
+#pragma unroll 4
+                for (int j = 0; j < Sh::PER_LANE; j++) {
+                    const int32_t e = wb + s + RPI * j;
+                    if (e < ce) {
+                        const double w = __builtin_nontemporal_load(a.rem_val + e);
+                        const int32_t col = __builtin_nontemporal_load(a.rem_col + e);
+                        const double xv = col_live ? X[(int64_t)col * ldx + c] : 0.0;
+                        s_prod[(e - cb) * KC + c] = __dmul_rn(w, xv);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < KC; q++) {
+                    const int64_t row = wave_base + s + RPI * q;
+                    if (row < n && col_live) {
+                        const int32_t rs = a.rem_ptr[row], re = a.rem_ptr[row + 1];
+                        const int32_t lo = rs > cb ? rs : cb;
+                        const int32_t hi = re < ce ? re : ce;
+                        for (int32_t e = lo; e < hi; e++)
+                            acc[q] = __dadd_rn(acc[q], s_prod[(e - cb) * KC + c]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    if (HAS_DIA && a.has_dia && wave_base < n) {
+        if (a.uniform) {
+            // all rows of this wavefront lie in block ib
+            const int64_t ib = wave_base / a.n_b;
+            const int32_t kb0 = uniform_load(a.dia_ptr, ib);
+            const int32_t kb1 = uniform_load(a.dia_ptr, ib + 1);
+            const int64_t t0 = wave_base - ib * a.n_b;
+            // the one-block (HDC) layout has no slots past row n - 1
+            const bool lrow = wave_base + lane < n;
+            for (int32_t kk = kb0; kk < kb1; kk += U) {
+                int64_t off[U];
+                double wl[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const bool live = kk + u < kb1;
+                    off[u] = uniform_load(a.dia_off, live ? kk + u : kb1 - 1);
+                    wl[u] = live && lrow ? __builtin_nontemporal_load(
+                                                   a.dia_val + (int64_t)(kk + u) * a.n_b + t0 + lane)
+                                         : 0.0;
+                }
+                double xv[U][KC];
+                bool in[U][KC];
+#pragma unroll
+                for (int u = 0; u < U; u++)
+#pragma unroll
+                    for (int q = 0; q < KC; q++) {
+                        const int64_t row = wave_base + s + RPI * q;
+                        const int64_t j = row + off[u];
+                        in[u][q] = kk + u < kb1 && row < n && j >= 0 && j < n && col_live;
+                        xv[u][q] = in[u][q] ? X[j * ldx + c] : 0.0;
+                    }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+#pragma unroll
+                    for (int q = 0; q < KC; q++) {
+                        const double w = __shfl(wl[u], s + RPI * q, 64);
+                        if (in[u][q])
+                            acc[q] = __dadd_rn(acc[q], __dmul_rn(w, xv[u][q]));
+                    }
+            }
+        } else {
+            // rows of one wavefront span several blocks: each row walks its
+            // own block's list
+#pragma unroll
+            for (int q = 0; q < KC; q++) {
+                const int64_t row = wave_base + s + RPI * q;
+                if (row < n && col_live) {
+                    const int64_t ib = row / a.n_b;
+                    const int64_t t = row - ib * a.n_b;
+                    const int32_t kb0 = a.dia_ptr[ib], kb1 = a.dia_ptr[ib + 1];
+                    for (int32_t kk = kb0; kk < kb1; kk++) {
+                        const int64_t j = row + a.dia_off[kk];
+                        if (j >= 0 && j < n) {
+                            const double w = a.dia_val[(int64_t)kk * a.n_b + t];
+                            acc[q] = __dadd_rn(acc[q], __dmul_rn(w, X[j * ldx + c]));
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+        const int64_t row = wave_base + s + RPI * q;
+        if (row < n && col_live)
+            __builtin_nontemporal_store(acc[q], a.Y + row * a.ldy + c);
+    }
+}
+
+}  // namespace mhdc

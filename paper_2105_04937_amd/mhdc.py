@@ -90,6 +90,7 @@ SIGNATURES = {
     "mhdc_from_csr": (_vp, [_i32, _vp, _vp, _vp, _i32, _f64]),
     "mhdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mhdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "mhdc_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "mhdc_to_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mhdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mhdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
@@ -99,6 +100,7 @@ SIGNATURES = {
     "hdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hdc_spmv_unblocked": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "hdc_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "hdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "hdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "hdc_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
@@ -106,6 +108,7 @@ SIGNATURES = {
     "csr_from_csr": (_vp, [_i32, _vp, _vp, _vp]),
     "csr_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "csr_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "csr_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "csr_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "csr_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
     "csr_destroy": (None, [_vp]),
@@ -240,6 +243,27 @@ class _Matrix:
             raise ValueError("Y must have shape (%d, %d)" % (k, self.n))
         _check(self._fn("spmm")(self._h, _dptr(X, torch.float64, "X"), self.n,
                                 _dptr(Y, torch.float64, "Y"), self.n, k, _stream(stream)))
+        return Y
+
+    def spmm_rowmajor(self, X, Y=None, stream=None):
+        """Y = A X for k right-hand sides stored row by row: X of shape
+        (n, ldx) with the k columns first (ldx >= k; a view X[:, :k] of a
+        wider row-major array is allowed), Y likewise (allocated (n, k) when
+        None)."""
+        if X.dim() != 2 or X.shape[0] != self.n or X.stride(1) != 1:
+            raise ValueError("X must be an (n, k) row-major view")
+        k = X.shape[1]
+        ldx = X.stride(0) if self.n > 1 else k
+        if Y is None:
+            Y = torch.empty((self.n, k), dtype=torch.float64, device=X.device)
+        if tuple(Y.shape) != (self.n, k) or Y.stride(1) != 1:
+            raise ValueError("Y must be an (%d, %d) row-major view" % (self.n, k))
+        ldy = Y.stride(0) if self.n > 1 else k
+        for t, name in ((X, "X"), (Y, "Y")):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("%s must be a float64 device tensor" % name)
+        _check(self._fn("spmm_rowmajor")(self._h, ctypes.c_void_p(X.data_ptr()), ldx,
+                                         ctypes.c_void_p(Y.data_ptr()), ldy, k, _stream(stream)))
         return Y
 
     def close(self):

@@ -1,0 +1,128 @@
+"""Several right-hand sides stored row by row (element (i, r) at
+X[i*ldx + r]): every column bit-identical to the oracle's sequential kernels
+(Figs. 3, 8, 16) and to the column-major product, for M-HDC (blocks that are
+and are not multiples of 64 rows), HDC and CSR handles, k = 1..16, padded
+leading dimensions, both workgroup sizes; the full-size 16-column cases of
+the benchmark; and the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_04937_amd import mhdc, synth
+from tests.gpu_helpers import assert_oracle_bits, assert_same_bits, dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    return [synth.random_csr(1, 1, density=1.0),
+            synth.random_csr(70, 2, density=0.05, bands=[0, 1, -3], int_values=True),
+            synth.random_csr(300, 3, density=0.02, bands=[0, 1, -1, 17, -40], zero_frac=0.1),
+            synth.random_csr(1000, 4, density=0.004, bands=[0, 1, -1, 30, -30, 300],
+                             band_fill=0.8),
+            synth.partially_diagonal(11, 5)]
+
+
+def _rm(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).cuda()
+
+
+def _check_cols(Y, want_cols, name):
+    Yh = Y.cpu().numpy()
+    for r, w in enumerate(want_cols):
+        assert_oracle_bits(np.ascontiguousarray(Yh[:, r]), w, "%s column %d" % (name, r))
+
+
+@pytest.mark.parametrize("i", range(len(_cases())))
+def test_rowmajor_matches_oracle(i):
+    m = _cases()[i]
+    say("case: row-major matrix %d n=%d nnz=%d" % (i, m.n, m.nnz))
+    d = dev(m)
+    rng = np.random.default_rng(10 + i)
+    mats = []
+    for bl in (1, 48, 64, 128, 1000):
+        ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, bl, 0.6)
+        mats.append(("mhdc bl=%d" % bl, mhdc.MHDCMatrix.from_csr(*d, bl, 0.6),
+                     lambda x, ref=ref: oracle.mhdc_spmv(ref, x)))
+    rh = oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6)
+    mats.append(("hdc", mhdc.HDCMatrix.from_csr(*d, 0.6), lambda x: oracle.hdc_spmv(rh, x)))
+    mats.append(("csr", mhdc.CSRMatrix.from_csr(*d),
+                 lambda x: oracle.csr_spmv(m.rowptr, m.colind, m.val, x)))
+    for k in (1, 2, 3, 5, 8, 11, 16):
+        X = rng.uniform(-1, 1, size=(m.n, k))
+        Xd = _rm(X)
+        for name, h, f in mats:
+            for wg in (64, 256):
+                h.set_launch(1, wg, 0 if wg == 64 else 16)
+                Y = h.spmm_rowmajor(Xd)
+                _check_cols(Y, want_for(f, X, k), "%s wg %d" % (name, wg))
+            Yc = h.spmm(_rm(X.T))  # column-major product of the same columns
+            assert_same_bits(Yc.cpu().numpy().T, Y.cpu().numpy(), "%s row- vs column-major" % name)
+    for _, h, _ in mats:
+        h.close()
+
+
+def want_for(f, X, k):
+    return [f(np.ascontiguousarray(X[:, r])) for r in range(k)]
+
+
+def test_rowmajor_padded_leading_dimensions():
+    m = synth.partially_diagonal(12, 6)
+    say("case: row-major padded ld n=%d" % m.n)
+    d = dev(m)
+    h = mhdc.MHDCMatrix.from_csr(*d, 128, 0.6)
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 128, 0.6)
+    rng = np.random.default_rng(6)
+    k = 5
+    Xw = rng.uniform(-1, 1, size=(m.n, 24))
+    Xd = _rm(Xw)[:, :k]
+    Yw = torch.full((m.n, 20), float("nan"), dtype=torch.float64, device="cuda")
+    h.spmm_rowmajor(Xd, Yw[:, :k])
+    _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
+                            for r in range(k)], "padded")
+    assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
+    # argument checks: ld below k, overlapping X and Y
+    buf = torch.zeros((m.n, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(mhdc.MhdcError) as e:
+        h.spmm_rowmajor(buf[:, :4], buf[:, 4:])
+    assert e.value.name == "MHDC_ERR_INVALID_ARG"
+    lib = mhdc.lib()
+    import ctypes
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = lib.mhdc_spmm_rowmajor(h._h, ctypes.c_void_p(buf.data_ptr()), 3,
+                                ctypes.c_void_p(Yw.data_ptr()), 20, 4, s)
+    assert rc == -1  # ldx < k
+    rc = lib.mhdc_spmm_rowmajor(h._h, ctypes.c_void_p(buf.data_ptr()), 8,
+                                ctypes.c_void_p(Yw.data_ptr()), 20, 17, s)
+    assert rc == -1  # k > 16
+    h.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("case", ["partial192_nb128", "hepta256_nb256"])
+def test_rowmajor_full_size_16(case):
+    """The benchmark's 16-column products at full size: every column equals
+    the column-major product's bits (itself pinned to the oracle in
+    test_gpu_full) and column 0 the oracle's Fig. 16 kernel."""
+    say("case: row-major full size %s" % case)
+    if case.startswith("partial"):
+        m, nb, seed = synth.partially_diagonal(192, 3), 128, 3
+    else:
+        m, nb, seed = synth.heptadiagonal(256, 2), 256, 2
+    d = dev(m)
+    h = mhdc.MHDCMatrix.from_csr(*d, nb, 0.6)
+    k = 16
+    Xc = torch.empty((k, m.n), dtype=torch.float64, device="cuda")
+    x0 = synth.vector(m.n, seed)
+    Xc[0] = torch.from_numpy(x0).cuda()
+    for r in range(1, k):
+        Xc[r] = torch.from_numpy(synth.vector(m.n, 100 + r)).cuda()
+    Yc = h.spmm(Xc)
+    Xr = Xc.t().contiguous()
+    del Xc
+    Yr = h.spmm_rowmajor(Xr)
+    assert torch.equal(Yr.t().contiguous().view(torch.int64), Yc.view(torch.int64))
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, nb, 0.6)
+    assert_oracle_bits(Yr[:, 0].contiguous(), oracle.mhdc_spmv(ref, x0), "column 0")
+    h.close()
