@@ -52,6 +52,45 @@ def time_steps(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def interleaved(fns, rounds, steps, warmup, stream):
+    """Median seconds per call of each function, timed in `rounds` rounds
+    that take the functions in turn (steps calls each), so that drifts of
+    clock or temperature fall on all of them alike."""
+    import statistics
+
+    import torch
+    for fn in fns.values():
+        for _ in range(warmup):
+            fn()
+    torch.cuda.synchronize()
+    ts = {k: [] for k in fns}
+    for _ in range(rounds):
+        for k, fn in fns.items():
+            ts[k].append(time_steps(fn, steps, 0, stream))
+    return {k: statistics.median(v) for k, v in ts.items()}
+
+
+def rocsparse_csrmv(m, d, x, stream):
+    """rocSPARSE's analysed CSR SpMV on the same device arrays as a
+    callable y = A x (the vendor's GPU CSR kernel, a point of reference for
+    the CSR baseline), or None without librocsparse.so."""
+    import torch
+    from paper_2105_04937_amd import vendor
+    if not vendor.available():
+        return None, None
+    rs = vendor.RocSparse(stream)
+    rp, ci, v = d
+    info = rs.analysis(m.n, m.nnz, rp, ci, v)
+    y = torch.empty_like(x)
+    fn = lambda: rs.csrmv(m.n, m.nnz, rp, ci, v, info, x, y)  # noqa: E731
+
+    def close():
+        torch.cuda.synchronize()
+        rs.free_info(info)
+        rs.close()
+    return fn, close
+
+
 def paper_protocol(fn, n_ites, n_loops, stream):
     """Sec. 6.1.3 / Fig. 18: best over n_loops of the mean over n_ites calls."""
     import torch
@@ -190,12 +229,28 @@ def main():
         cs.close()
         out["csr"] = {"gflops": round(2 * inf_c["nnz"] / t_csr / 1e9, 2),
                       "gb_per_s": round(inf_c["bytes_alg"] / t_csr / 1e9, 1),
-                      "us_per_step": round(t_csr * 1e6, 2), "bytes_alg": inf_c["bytes_alg"]}
+                      "us_per_step": round(t_csr * 1e6, 2), "bytes_alg": inf_c["bytes_alg"],
+                      "roofline_frac": round(inf_c["bytes_alg"] / t_csr / 1e9 / PEAK_HBM_GBS, 4)}
+        # the vendor's analysed csrmv on the same arrays: the speed-up is
+        # quoted against the faster of the two GPU CSR kernels
+        t_best_csr = t_csr
+        vfn, vclose = rocsparse_csrmv(m, (rp, ci, v), x, stream)
+        if vfn:
+            t_vs = time_steps(vfn, args.steps, args.warmup, stream)
+            vclose()
+            log("rocSPARSE csrmv (analysed) %8.3f us/step  %7.1f GB/s" % (
+                t_vs * 1e6, inf_c["bytes_alg"] / t_vs / 1e9))
+            out["csr"]["rocsparse_analysed_us"] = round(t_vs * 1e6, 2)
+            out["csr"]["rocsparse_roofline_frac"] = round(
+                inf_c["bytes_alg"] / t_vs / 1e9 / PEAK_HBM_GBS, 4)
+            t_best_csr = min(t_csr, t_vs)
         out["hdc"] = {"gflops": round(2 * inf_h["nnz"] / t_hdc / 1e9, 2),
                       "gb_per_s": round(inf_h["bytes_alg"] / t_hdc / 1e9, 1),
                       "us_per_step": round(t_hdc * 1e6, 2), "K": inf_h["K"]}
-        out["speedup_vs_csr"] = round(t_csr / t_mhdc, 4)
+        out["speedup_vs_csr"] = round(t_best_csr / t_mhdc, 4)
+        out["speedup_vs_library_csr"] = round(t_csr / t_mhdc, 4)
         out["speedup_vs_csr_model"] = round(inf["rp_est"], 4)
+        out["mhdc_roofline_frac"] = round(inf["bytes_alg"] / t_mhdc / 1e9 / PEAK_HBM_GBS, 4)
         # block size sweep on the same matrix (default launch of each handle)
         sweep = {str(args.n_b): {"us": round(t_mhdc * 1e6, 2),
                                  "gb_per_s": round(inf["bytes_alg"] / t_mhdc / 1e9, 1),
@@ -241,7 +296,6 @@ def main():
             h3.close()
         c3, _, tc3, _, ic3 = run_format(lambda: mhdc.CSRMatrix.from_csr(*d3), x3,
                                         args.steps // 2, args.warmup, stream, "CSR")
-        c3.close()
         hd3, _, th3, _, ih3 = run_format(lambda: mhdc.HDCMatrix.from_csr(*d3, 0.6), x3,
                                          args.steps // 2, args.warmup, stream, "HDC")
         hd3.close()
@@ -253,24 +307,38 @@ def main():
         from paper_2105_04937_amd import learned
         hsel, dec = mhdc.select(*d3, model=learned.load_network(),
                                 tolerance=learned.JUDGE_TOLERANCE)
-        ys = torch.empty_like(x3)
-        ts = time_steps(lambda: hsel.spmv(x3, ys, stream), args.steps // 2, args.warmup, stream)
         res["mhdc_selected"] = {"theta": dec["theta"], "n_b": dec["n_b"],
-                                "used_rule": bool(dec["used_rule"]), "us": round(ts * 1e6, 2),
-                                "gflops": round(2 * m3.nnz / ts / 1e9, 2)}
-        log("selected theta=%.1f n_b=%d %8.3f us/step" % (dec["theta"], dec["n_b"], ts * 1e6))
-        hsel.close()
+                                "used_rule": bool(dec["used_rule"])}
         # the same choice refined by timing its grid neighbours on the device
         href, dref = mhdc.select_refine(*d3, model=learned.load_network(),
                                         tolerance=learned.JUDGE_TOLERANCE, stream=stream)
-        tr = time_steps(lambda: href.spmv(x3, ys, stream), args.steps // 2, args.warmup, stream)
         res["mhdc_refined"] = {"theta": dref["theta"], "n_b": dref["n_b"],
-                               "used_rule": bool(dref["used_rule"]), "us": round(tr * 1e6, 2),
-                               "gflops": round(2 * m3.nnz / tr / 1e9, 2)}
-        log("refined  theta=%.1f n_b=%d %8.3f us/step" % (dref["theta"], dref["n_b"], tr * 1e6))
-        href.close()
-        best = min(v_["us"] for k_, v_ in res.items() if k_.startswith("mhdc"))
-        res["speedup_best_mhdc_vs_csr"] = round(res["csr"]["us"] / best, 4)
+                               "used_rule": bool(dref["used_rule"])}
+        # M-HDC against GPU CSR: the pre-declared configuration (n_b = 128,
+        # theta = 0.6) and the selector's choices, timed in interleaved
+        # rounds with the library's CSR and rocSPARSE's analysed csrmv
+        h128 = mhdc.MHDCMatrix.from_csr(*d3, 128, 0.6)
+        ya, yb, yc, yd = (torch.empty_like(x3) for _ in range(4))
+        fns = {"mhdc_nb128": lambda: h128.spmv(x3, ya, stream),
+               "selected": lambda: hsel.spmv(x3, yb, stream),
+               "refined": lambda: href.spmv(x3, yc, stream),
+               "csr": lambda: c3.spmv(x3, yd, stream)}
+        vfn, vclose = rocsparse_csrmv(m3, d3, x3, stream)
+        if vfn:
+            fns["rocsparse"] = vfn
+        ti = interleaved(fns, 5, max(args.steps // 10, 1), args.warmup, stream)
+        if vclose:
+            vclose()
+        t_best_csr = min(ti["csr"], ti.get("rocsparse", float("inf")))
+        res["interleaved_us"] = {k: round(v_ * 1e6, 2) for k, v_ in ti.items()}
+        res["mhdc_selected"]["us"] = res["interleaved_us"]["selected"]
+        res["mhdc_refined"]["us"] = res["interleaved_us"]["refined"]
+        res["speedup_mhdc_nb128_vs_csr"] = round(t_best_csr / ti["mhdc_nb128"], 4)
+        res["speedup_selected_vs_csr"] = round(t_best_csr / ti["selected"], 4)
+        res["speedup_refined_vs_csr"] = round(t_best_csr / ti["refined"], 4)
+        log("interleaved: %s" % res["interleaved_us"])
+        for hh in (h128, hsel, href, c3):
+            hh.close()
         res["workload"] = "27-point 192^3, octant drops {0,.05,.1,.2,.3,.5,.7,.9}, +2 random/row"
         res["nnz"] = m3.nnz
         partial = res

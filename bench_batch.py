@@ -3,6 +3,7 @@ its own number of right-hand sides, in one persistent launch replayed from a
 HIP graph, against 64 separate launches.
 
     python bench_batch.py [--count 64] [--steps K] [--warmup W]
+                          [--layouts colmajor,rowmajor]
 
 Matrices: grid side U{16..96}, stencil drawn from {7, 19, 27} points, one
 drop probability U[0, 0.3], values N(0,1), diagonal 1.1*|row sum|, k ~
@@ -10,6 +11,8 @@ U{1..16} right-hand sides; matrix i uses seed 4000 + i.  The autotuner
 (mhdc_autotune) picks n_b and the launch shape per matrix from timed runs;
 mhdc_batch_tune picks the batch's workgroup size.  A step is one product of
 all matrices with all their right-hand sides, inputs resident in HBM.
+Right-hand sides are column-major (k_i rows of n_i) or stored row by row
+(n_i rows of k_i, the row-major batch kernel); both are timed.
 
 Prints one JSON line; value = GFLOP/s = sum_i 2*nnz_i*k_i / (time per step).
 """
@@ -51,7 +54,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.6)
+    ap.add_argument("--layouts", default="colmajor,rowmajor")
     args = ap.parse_args()
+    layouts = args.layouts.split(",")
 
     import numpy as np
     import torch
@@ -79,21 +84,31 @@ def main():
         if i % 8 == 7:
             log("prepared %d matrices" % (i + 1))
 
-    def separate(mats, Ys):
+    Xs_rm = [X.t().contiguous() for X in Xs] if "rowmajor" in layouts else []
+
+    def separate(mats, Xl, Ys, rowmajor):
         def f():
-            for h, X, Y in zip(mats, Xs, Ys):
-                h.spmm(X, Y, stream)
+            for h, X, Y in zip(mats, Xl, Ys):
+                if rowmajor:
+                    h.spmm_rowmajor(X, Y, stream)
+                else:
+                    h.spmm(X, Y, stream)
         return f
 
     res = {}
-    for label, mats in (("autotuned", tuned), ("n_b256", fixed)):
-        b = mhdc.Batch(mats, Xs)
+    runs = [(lab, mats, lay) for lay in layouts
+            for lab, mats in (("autotuned", tuned), ("n_b256", fixed))]
+    for label, mats, lay in runs:
+        rowmajor = lay == "rowmajor"
+        Xl = Xs_rm if rowmajor else Xs
+        label = label if not rowmajor else label + "_rowmajor"
+        b = mhdc.Batch(mats, Xl, layout=lay)
         wg, _ = b.tune(stream)
         info = b.info()
         t_graph = timed(lambda: b.graph_launch(stream), args.steps, args.warmup, stream)
         t_run = timed(lambda: b.run(stream), args.steps, args.warmup, stream)
-        Ys_sep = [torch.empty_like(X) for X in Xs]
-        t_sep = timed(separate(mats, Ys_sep), args.steps, args.warmup, stream)
+        Ys_sep = [torch.empty_like(X) for X in Xl]
+        t_sep = timed(separate(mats, Xl, Ys_sep, rowmajor), args.steps, args.warmup, stream)
         b.run(stream)
         torch.cuda.synchronize()
         same = all(torch.equal(a.view(torch.int64), c.view(torch.int64))
@@ -112,7 +127,7 @@ def main():
             info["bytes_alg"] / t_graph / 1e9))
         b.close()
 
-    best = res["autotuned"]
+    best = res["autotuned" if "colmajor" in layouts else "autotuned_rowmajor"]
     rec = {
         "metric": "batched M-HDC SpMM GFLOP/s (one persistent hipGraph launch), FP64, 1xMI355X",
         "value": best["gflops_graph"], "unit": "GFLOP/s", "n_gpus": 1,

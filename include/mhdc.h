@@ -271,6 +271,17 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats,
                              const int32_t *nrhs, const double *const *X,
                              const int64_t *ldx, double *const *Y,
                              const int64_t *ldy, int32_t wg_size);
+/* As mhdc_batch_create for right-hand sides stored row by row: X[i] holds
+ * n_i rows of nrhs[i] values, row r at X[i] + r*ldx[i] with ldx[i] >=
+ * nrhs[i] (NULL ldx/ldy = nrhs[i]), as in mhdc_spmm_rowmajor; item i's
+ * result is bit-identical to mhdc_spmm_rowmajor(mats[i], X[i], ldx[i],
+ * Y[i], ldy[i], nrhs[i]).  The layout is the batch's for its lifetime
+ * (mhdc_batch_bind takes pointers of the same layout). */
+mhdc_batch mhdc_batch_create_rowmajor(int32_t count, const mhdc_handle *mats,
+                                      const int32_t *nrhs,
+                                      const double *const *X, const int64_t *ldx,
+                                      double *const *Y, const int64_t *ldy,
+                                      int32_t wg_size);
 /* Replace the X/Y pointers (synchronous; waits for work in flight).  A
  * captured graph reads the table from device memory and sees the change.
  * On failure the batch keeps its previous binding and stays runnable. */
@@ -390,7 +401,29 @@ typedef struct {
     int32_t net_ok;        /* 0 if the network gave a non-finite output */
     double bytes_net;      /* model volume V of the proposal */
     double bytes_rule;     /* model volume V of the policy */
+    /* The byte model's verdict on the chosen layout against plain CSR
+     * (Sec. 5.3), the question of whether to use M-HDC at all (Sec. 7): */
+    double rp_est;         /* V_CSR / V of the choice (1 + Eq. 28, v_x = 1) */
+    double alpha, beta;    /* filling rate and CSR rate of the choice (Eq. 33) */
+    int32_t csr_cheaper;   /* 1 if V_CSR < V, i.e. alpha < 1/(1+b) = 2/3
+                              (Eqs. 31-32): plain CSR moves fewer bytes */
+    int32_t reserved;
 } mhdc_select_result;
+
+/* The judge of mhdc_select, exposed so that offline evaluations apply the
+ * same rule: 1 if a proposal whose model volume is v_proposal is kept
+ * against the policy's v_policy (v_proposal <= (1 + tolerance) v_policy),
+ * else 0.  Host-only; needs no GPU. */
+int mhdc_judge_keep(double v_proposal, double v_policy, double tolerance);
+
+/* The candidates mhdc_select_refine times besides the decision (theta,
+ * n_b): n_b halved and doubled, theta -+ 0.1, the policy (0.6, 256) and
+ * (theta, 4096), each kept only inside the grid of Sec. 6.4.1 (theta in
+ * 0.5 .. 0.9, n_b in 32 .. 4096) and only once, the decision itself left
+ * out.  Writes up to `cap` pairs and returns how many there are (at most
+ * 6).  Host-only; needs no GPU. */
+int32_t mhdc_refine_candidates(double theta, int32_t n_b, double *theta_out,
+                               int32_t *n_b_out, int32_t cap);
 
 /* Choose (theta, n_b) and convert.  model = NULL uses the policy.  The
  * proposal is kept unless its V exceeds (1 + tolerance) x the policy's V.

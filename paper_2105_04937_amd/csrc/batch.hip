@@ -14,6 +14,7 @@
 // pointers takes effect in later replays without re-capture.
 #include "internal.h"
 #include "spmv_tile.h"
+#include "spmv_tile_rm.h"
 
 #include <algorithm>
 #include <new>
@@ -70,7 +71,29 @@ __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *ld
     }
 }
 
+// Row-major right-hand sides: the row-slot tile routine at the item's width.
+template <int WG, int KC>
+__device__ inline void batch_tile_rm(const BatchItem &it, int64_t local, double *lds)
+{
+    spmv_tile_rm<WG, KC, true, true>(it.a, local, lds);
+}
+
 __global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
+
+// Item owning global tile t: the last item with tile_begin <= t.
+__device__ inline int32_t batch_item_of(const BatchItem *__restrict__ items, int32_t count,
+                                        int64_t t)
+{
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (uniform_load(&items[mid].tile_begin, 0) <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 // Four waves per SIMD (at most 128 VGPRs): uncapped, the compiler took 132
 // and the machine held three 256-lane workgroups per CU, which measured 6%
@@ -89,16 +112,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         __syncthreads();
         if (t >= total_tiles)
             break;  // the counter only grows: every workgroup reaches this
-        // item owning tile t: last item with tile_begin <= t
-        int32_t lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (uniform_load(&items[mid].tile_begin, 0) <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const BatchItem &it = items[lo];
+        const BatchItem &it = items[batch_item_of(items, count, t)];
         const int64_t local = t - it.tile_begin;
         switch (it.kc) {
         case 1: batch_tile<WG, 1>(it, local, s_prod); break;
@@ -106,6 +120,37 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         case 4: batch_tile<WG, 4>(it, local, s_prod); break;
         case 8: batch_tile<WG, 8>(it, local, s_prod); break;
         default: batch_tile<WG, 16>(it, local, s_prod); break;
+        }
+    }
+}
+
+// The persistent loop for a batch whose right-hand sides are stored row by
+// row.  A kernel of its own: its tile routine keeps KC rows per lane in
+// registers and would not fit the column-major kernel's register cap.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_batch_rm(const BatchItem *__restrict__ items,
+                                                 int32_t count, int64_t total_tiles,
+                                                 int32_t *counter)
+{
+    __shared__ double s_prod[TileShapeRm<WG, 2>::LDS_BYTES / 8];
+    static_assert(TileShapeRm<WG, 2>::LDS_BYTES == TileShapeRm<WG, 16>::LDS_BYTES,
+                  "one LDS size for every width");
+    __shared__ int64_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t t = s_tile;
+        __syncthreads();
+        if (t >= total_tiles)
+            break;  // the counter only grows: every workgroup reaches this
+        const BatchItem &it = items[batch_item_of(items, count, t)];
+        const int64_t local = t - it.tile_begin;
+        switch (it.kc) {
+        case 2: batch_tile_rm<WG, 2>(it, local, s_prod); break;
+        case 4: batch_tile_rm<WG, 4>(it, local, s_prod); break;
+        case 8: batch_tile_rm<WG, 8>(it, local, s_prod); break;
+        default: batch_tile_rm<WG, 16>(it, local, s_prod); break;
         }
     }
 }
@@ -128,21 +173,27 @@ struct mhdc_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double flops = 0, bytes_alg = 0;
+    int32_t rowmajor = 0;  // right-hand sides stored row by row
 };
 
 namespace {
 
-int batch_grid(int wg, int64_t total_tiles, int32_t *grid)
+const void *batch_kernel(int wg, int rowmajor)
+{
+    if (rowmajor)
+        return wg == 64 ? reinterpret_cast<const void *>(k_batch_rm<64>)
+                        : reinterpret_cast<const void *>(k_batch_rm<256>);
+    return wg == 64 ? reinterpret_cast<const void *>(k_batch<64>)
+                    : reinterpret_cast<const void *>(k_batch<256>);
+}
+
+int batch_grid(int wg, int rowmajor, int64_t total_tiles, int32_t *grid)
 {
     int dev = 0, cus = 0, per_cu = 0;
     MHDC_HIP_CHECK(hipGetDevice(&dev));
     MHDC_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (wg == 64)
-        MHDC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_batch<64>), 64, 0));
-    else
-        MHDC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_batch<256>), 256, 0));
+    MHDC_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, batch_kernel(wg, rowmajor), wg, 0));
     int64_t g = (int64_t)cus * std::max(per_cu, 1);
     if (g > total_tiles)
         g = total_tiles;
@@ -167,13 +218,15 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
     for (int32_t i = 0; i < b->count; i++) {
         const BdcMatrix &m = *b->mats[i];
         const int32_t k = b->nrhs[i];
-        const int64_t lx = ldx ? ldx[i] : m.n, ly = ldy ? ldy[i] : m.n;
-        int rc = check_operands(m, X[i], lx, Y[i], ly, k);
+        const int64_t dflt = b->rowmajor ? k : m.n;
+        const int64_t lx = ldx ? ldx[i] : dflt, ly = ldy ? ldy[i] : dflt;
+        int rc = b->rowmajor ? check_operands_rm(m, X[i], lx, Y[i], ly, k)
+                             : check_operands(m, X[i], lx, Y[i], ly, k);
         if (rc)
             return rc;
         BatchItem &it = items[i];
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
-        it.kc = kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
+        it.kc = b->rowmajor ? rm_columns(k) : kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
         it.rg = row_gather(m.launch.csr_mode, it.kc) ? 1 : 0;
         it.tile_begin = tiles;
         tiles += ((int64_t)m.n + wg - 1) / wg;
@@ -183,7 +236,7 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
     if (tiles > BATCH_MAX_TILES)
         return set_error(MHDC_ERR_SIZE, "too many tiles in the batch");
     int32_t grid = 0;
-    int rc = batch_grid(wg, tiles, &grid);
+    int rc = batch_grid(wg, b->rowmajor, tiles, &grid);
     if (rc)
         return rc;
     MHDC_HIP_CHECK(hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * b->count,
@@ -202,7 +255,12 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
     if (b->total_tiles == 0)
         return MHDC_OK;
     k_batch_reset<<<1, 1, 0, s>>>(b->d_counter);
-    if (b->wg == 64)
+    if (b->rowmajor && b->wg == 64)
+        k_batch_rm<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+    else if (b->rowmajor)
+        k_batch_rm<256><<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles,
+                                                b->d_counter);
+    else if (b->wg == 64)
         k_batch<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
     else
         k_batch<256><<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
@@ -211,6 +269,10 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
         return set_error(MHDC_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
     return MHDC_OK;
 }
+
+mhdc_batch batch_create(int32_t count, const mhdc_handle *mats, const int32_t *nrhs,
+                        const double *const *X, const int64_t *ldx, double *const *Y,
+                        const int64_t *ldy, int32_t wg_size, int32_t rowmajor);
 
 void drop_graph(mhdc_batch_s *b)
 {
@@ -230,6 +292,25 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats, const int32
                              const double *const *X, const int64_t *ldx, double *const *Y,
                              const int64_t *ldy, int32_t wg_size)
 {
+    return batch_create(count, mats, nrhs, X, ldx, Y, ldy, wg_size, 0);
+}
+
+mhdc_batch mhdc_batch_create_rowmajor(int32_t count, const mhdc_handle *mats,
+                                      const int32_t *nrhs, const double *const *X,
+                                      const int64_t *ldx, double *const *Y, const int64_t *ldy,
+                                      int32_t wg_size)
+{
+    return batch_create(count, mats, nrhs, X, ldx, Y, ldy, wg_size, 1);
+}
+
+}  // extern "C"
+
+namespace {
+
+mhdc_batch batch_create(int32_t count, const mhdc_handle *mats, const int32_t *nrhs,
+                        const double *const *X, const int64_t *ldx, double *const *Y,
+                        const int64_t *ldy, int32_t wg_size, int32_t rowmajor)
+{
     clear_error();
     if (count < 1 || !mats || !nrhs || !X || !Y) {
         set_error(MHDC_ERR_INVALID_ARG, "count >= 1 and non-NULL mats, nrhs, X, Y required");
@@ -246,6 +327,7 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats, const int32
     }
     b->count = count;
     b->wg = wg_size;
+    b->rowmajor = rowmajor;
     for (int32_t i = 0; i < count; i++) {
         if (!mats[i] || nrhs[i] < 1 || nrhs[i] > 16) {
             set_error(MHDC_ERR_INVALID_ARG, "matrix handle NULL or nrhs outside [1, 16]");
@@ -268,6 +350,10 @@ mhdc_batch mhdc_batch_create(int32_t count, const mhdc_handle *mats, const int32
     }
     return b;
 }
+
+}  // namespace
+
+extern "C" {
 
 int mhdc_batch_bind(mhdc_batch b, const double *const *X, const int64_t *ldx, double *const *Y,
                     const int64_t *ldy)

@@ -275,6 +275,23 @@ __global__ void k_decode(const float *__restrict__ out, int B, double *theta, in
     nb[r] = 1 << (int)l;
 }
 
+// Most candidates mhdc_refine_candidates can return.
+constexpr int32_t MAX_REFINE = 6;
+
+// The byte model's verdict on a chosen handle against plain CSR: its V_CSR /
+// V (Eq. 28), alpha, beta, and whether CSR moves fewer bytes -- exactly when
+// 3 (nnz - R) < 2 S, i.e. alpha < 2/3 (Eqs. 31-32), decided in integers.
+void set_verdict(mhdc_handle h, mhdc_select_result *res)
+{
+    mhdc_info inf{};
+    if (mhdc_get_info(h, &inf) != MHDC_OK)
+        return;
+    res->rp_est = inf.rp_est;
+    res->alpha = inf.alpha;
+    res->beta = inf.beta;
+    res->csr_cheaper = inf.S > 0 && 3 * (inf.nnz - inf.R) < 2 * inf.S ? 1 : 0;
+}
+
 // Hidden activations of the forward pass that allocates nothing
 // (mhdc_mlp_forward_noalloc): two layers of at most NOALLOC_MAX_B rows of
 // HID floats, 2 MB in all.  Each GPU the library runs on holds its own copy
@@ -696,7 +713,7 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
         res.bytes_net = in.bytes_paper;
         // the paper's byte model judges: keep the network's choice unless
         // it is predicted to move more than (1 + tolerance) x the policy's
-        if (in.bytes_paper <= (1.0 + tolerance) * ir.bytes_paper) {
+        if (mhdc_judge_keep(in.bytes_paper, ir.bytes_paper, tolerance)) {
             pick = net;
             res.theta = res.theta_net;
             res.n_b = res.n_b_net;
@@ -707,6 +724,7 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
         mhdc_destroy(rule);
     if (net && pick != net)
         mhdc_destroy(net);
+    set_verdict(pick, &res);
     if (out)
         *out = res;
     return pick;
@@ -734,26 +752,13 @@ mhdc_handle mhdc_select_refine(int32_t n, const int32_t *rowptr, const int32_t *
         int32_t n_b;
     };
     std::vector<Cand> cand;
-    auto add = [&](double th, int32_t nb) {
-        th = std::round(th * 10.0) / 10.0;
-        if (th < 0.5 - 1e-9 || th > 0.9 + 1e-9 || nb < 32 || nb > 4096)
-            return;
-        if (std::fabs(th - res.theta) < 1e-9 && nb == res.n_b)
-            return;
-        for (const Cand &c : cand)
-            if (std::fabs(c.theta - th) < 1e-9 && c.n_b == nb)
-                return;
-        cand.push_back({th, nb});
-    };
-    add(res.theta, res.n_b / 2);
-    add(res.theta, res.n_b * 2);
-    add(res.theta - 0.1, res.n_b);
-    add(res.theta + 0.1, res.n_b);
-    add(0.6, 256);
-    // the largest block of the grid: on matrices of a few 1e5 rows (10-30 us
-    // products) the fewest, longest segments often win by 5-20 %, far from
-    // the network's choice
-    add(res.theta, 4096);
+    {
+        double th[MAX_REFINE];
+        int32_t nb[MAX_REFINE];
+        const int32_t nc = mhdc_refine_candidates(res.theta, res.n_b, th, nb, MAX_REFINE);
+        for (int32_t c = 0; c < nc; c++)
+            cand.push_back({th[c], nb[c]});
+    }
     double *x = nullptr, *y = nullptr;
     int rc = dmalloc((void **)&x, sizeof(double) * (size_t)n, "refine x");
     if (!rc)
@@ -792,9 +797,52 @@ mhdc_handle mhdc_select_refine(int32_t n, const int32_t *rowptr, const int32_t *
         set_error(rc, "select refine: " + msg);
         return nullptr;
     }
+    set_verdict(best, &res);
     if (out)
         *out = res;
     return best;
+}
+
+int mhdc_judge_keep(double v_proposal, double v_policy, double tolerance)
+{
+    return v_proposal <= (1.0 + tolerance) * v_policy ? 1 : 0;
+}
+
+int32_t mhdc_refine_candidates(double theta, int32_t n_b, double *theta_out, int32_t *n_b_out,
+                               int32_t cap)
+{
+    double th[MAX_REFINE];
+    int32_t nb[MAX_REFINE];
+    int32_t cnt = 0;
+    auto add = [&](double t, int64_t b) {
+        t = std::round(t * 10.0) / 10.0;
+        if (t < 0.5 - 1e-9 || t > 0.9 + 1e-9 || b < 32 || b > 4096)
+            return;
+        if (std::fabs(t - theta) < 1e-9 && b == n_b)
+            return;
+        for (int32_t c = 0; c < cnt; c++)
+            if (std::fabs(th[c] - t) < 1e-9 && nb[c] == b)
+                return;
+        th[cnt] = t;
+        nb[cnt] = (int32_t)b;
+        cnt++;
+    };
+    add(theta, n_b / 2);
+    add(theta, (int64_t)n_b * 2);
+    add(theta - 0.1, n_b);
+    add(theta + 0.1, n_b);
+    add(0.6, 256);
+    // the largest block of the grid: on matrices of a few 1e5 rows (10-30 us
+    // products) the fewest, longest segments often win by 5-20 %, far from
+    // the network's choice
+    add(theta, 4096);
+    for (int32_t c = 0; c < cnt && c < cap; c++) {
+        if (theta_out)
+            theta_out[c] = th[c];
+        if (n_b_out)
+            n_b_out[c] = nb[c];
+    }
+    return cnt;
 }
 
 }  // extern "C"

@@ -190,8 +190,13 @@ def train(recs, steps=8000, B=128, lr=1e-3, seed=0):
 
 def evaluate(net, recs, tolerance=JUDGE_TOLERANCE):
     """Per held-out matrix: time of the judged network choice, of the policy
-    and of the exhaustive best, all from the measured grid."""
+    and of the exhaustive best, all from the measured grid.  The judge and
+    the refinement candidates are the library's own (mhdc_judge_keep,
+    mhdc_refine_candidates), so this evaluates exactly what mhdc_select and
+    mhdc_select_refine decide."""
     import torch
+
+    from paper_2105_04937_amd import mhdc
     X = torch.from_numpy(np.array([r["features"] for r in recs], np.float32)).cuda()
     th, nb, ok = (t.cpu().numpy() for t in net.decide(X))
     rows = []
@@ -200,22 +205,19 @@ def evaluate(net, recs, tolerance=JUDGE_TOLERANCE):
         kb = min(us, key=us.get)
         kr = key(*RULE)
         kn = key(float(t_), int(b_))
-        use_net = bool(o_) and r["bytes_paper"][kn] <= (1.0 + tolerance) * r["bytes_paper"][kr]
+        use_net = bool(o_) and mhdc.judge_keep(r["bytes_paper"][kn], r["bytes_paper"][kr],
+                                               tolerance)
         ks = kn if use_net else kr
-        # mhdc_select_refine's candidates: the choice, its grid neighbours,
-        # the policy and the choice's theta at n_b = 4096; the fastest by
+        # mhdc_select_refine: the choice and its candidates, the fastest by
         # the measured grid
         th_s, nb_s = (float(t_), int(b_)) if use_net else RULE
-        cands = {ks, kr}
-        for th2, nb2 in ((th_s, nb_s // 2), (th_s, nb_s * 2), (th_s - 0.1, nb_s),
-                         (th_s + 0.1, nb_s), (th_s, 4096)):
-            th2 = round(th2, 1)
-            if 0.5 - 1e-9 <= th2 <= 0.9 + 1e-9 and 32 <= nb2 <= 4096:
-                cands.add(key(th2, nb2))
+        cands = {ks} | {key(a, b) for a, b in mhdc.refine_candidates(th_s, nb_s)}
         kf = min(cands, key=us.get)
+        # the byte model's verdict on the selection against plain CSR
+        v_csr = 12.0 * r["nnz"] + 20.0 * r["n"]
         rows.append(dict(id=r["id"], best=kb, net=kn, used_net=use_net, refined=kf,
                          t_best=us[kb], t_sel=us[ks], t_rule=us[kr], t_net=us[kn],
-                         t_refined=us[kf]))
+                         t_refined=us[kf], csr_cheaper=v_csr < r["bytes_paper"][ks]))
     t_best = np.array([x["t_best"] for x in rows])
     t_sel = np.array([x["t_sel"] for x in rows])
     t_rule = np.array([x["t_rule"] for x in rows])
@@ -234,8 +236,37 @@ def evaluate(net, recs, tolerance=JUDGE_TOLERANCE):
         total_time_selected_us=float(t_sel.sum()), total_time_rule_us=float(t_rule.sum()),
         total_time_best_us=float(t_best.sum()),
         used_network=float(np.mean([x["used_net"] for x in rows])),
+        judge_override_rate=float(np.mean([not x["used_net"] for x in rows])),
+        within_5pct_network_unjudged=float(np.mean(t_net <= 1.05 * t_best)),
+        byte_model_prefers_csr=float(np.mean([x["csr_cheaper"] for x in rows])),
     )
     return rep, rows
+
+
+def report(net, recs, test, test_paths, train_meta):
+    """Held-out evaluation of a trained network, the training-set figures
+    beside it, the judge's tolerance sweep on both sets (the tolerance is
+    chosen on the training set) and the best fixed grid point."""
+    rep, _ = evaluate(net, test)
+    rep_train, _ = evaluate(net, recs)
+    judge, judge_train = {}, {}
+    for tol in (0.0, 0.05, 0.10, 0.25, 1e9):
+        for dst, rs in ((judge, test), (judge_train, recs)):
+            r_, _ = evaluate(net, rs, tolerance=tol)
+            dst["%g" % tol] = {k: r_[k] for k in ("within_5pct_selected", "mean_ratio_selected",
+                                                  "used_network", "judge_override_rate")}
+    prior = prior_point(recs)
+    ks = list(test[0]["us"])
+    R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in test])
+    rep.update(judge_tolerance=JUDGE_TOLERANCE, train_matrices=len(recs), prior=prior,
+               prior_fixed_on_test=dict(mean_ratio=float(R[:, ks.index(prior)].mean()),
+                                        within_5pct=float(np.mean(R[:, ks.index(prior)] <= 1.05))),
+               judge_tolerance_sweep=judge, judge_tolerance_sweep_train=judge_train,
+               train_set=rep_train, **train_meta)
+    if len(test_paths) > 1:  # one summary per held-out file as well
+        rep["per_test_file"] = {os.path.basename(t): evaluate(net, load([t]))[0]
+                                for t in test_paths}
+    return rep
 
 
 def main(argv=None):
@@ -252,6 +283,11 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=8000)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--out-dir", required=True)
+    e = sub.add_parser("evaluate", help="re-evaluate stored weights (no training)")
+    e.add_argument("--data", nargs="+", required=True)
+    e.add_argument("--test", nargs="+", required=True)
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     if a.cmd == "collect":
@@ -259,33 +295,26 @@ def main(argv=None):
         return
     recs = load(a.data)
     test = load(a.test)
+    if a.cmd == "evaluate":
+        meta = {}
+        if os.path.exists(a.out):  # keep the training record of the weights
+            with open(a.out) as f:
+                old = json.load(f)
+            meta = {k: old[k] for k in ("train_steps", "train_seconds", "loss_first",
+                                         "loss_last") if k in old}
+        rep = report(load_network(a.weights), recs, test, a.test, meta)
+        with open(a.out, "w") as f:
+            json.dump(rep, f, indent=1)
+        print(json.dumps(rep))
+        return
     t0 = time.time()
     net, hist, prior = train(recs, steps=a.steps, lr=a.lr)
     dt = time.time() - t0
     os.makedirs(a.out_dir, exist_ok=True)
     np.save(os.path.join(a.out_dir, "weights.npy"), net.params())
-    rep, rows = evaluate(net, test)
-    rep_train, _ = evaluate(net, recs)
-    # the judge's tolerance is chosen on the training set; the held-out sweep
-    # is reported beside it
-    judge, judge_train = {}, {}
-    for tol in (0.0, 0.05, 0.10, 0.25, 1e9):
-        for dst, rs in ((judge, test), (judge_train, recs)):
-            r_, _ = evaluate(net, rs, tolerance=tol)
-            dst["%g" % tol] = {k: r_[k] for k in ("within_5pct_selected", "mean_ratio_selected",
-                                                  "used_network")}
-    ks = list(test[0]["us"])
-    R = np.array([[r["us"][k] / min(r["us"].values()) for k in ks] for r in test])
-    rep.update(judge_tolerance=JUDGE_TOLERANCE,
-               train_matrices=len(recs), train_steps=a.steps, train_seconds=round(dt, 2),
-               loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean()),
-               prior=prior, prior_fixed_on_test=dict(
-                   mean_ratio=float(R[:, ks.index(prior)].mean()),
-                   within_5pct=float(np.mean(R[:, ks.index(prior)] <= 1.05))),
-               judge_tolerance_sweep=judge, judge_tolerance_sweep_train=judge_train,
-               train_set=rep_train)
-    if len(a.test) > 1:  # one summary per held-out file as well
-        rep["per_test_file"] = {os.path.basename(t): evaluate(net, load([t]))[0] for t in a.test}
+    rep = report(net, recs, test, a.test,
+                 dict(train_steps=a.steps, train_seconds=round(dt, 2),
+                      loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean())))
     with open(os.path.join(a.out_dir, "eval_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep))

@@ -66,7 +66,10 @@ class SelectResult(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("n_b", ctypes.c_int32),
                 ("used_rule", ctypes.c_int32), ("theta_net", ctypes.c_double),
                 ("n_b_net", ctypes.c_int32), ("net_ok", ctypes.c_int32),
-                ("bytes_net", ctypes.c_double), ("bytes_rule", ctypes.c_double)]
+                ("bytes_net", ctypes.c_double), ("bytes_rule", ctypes.c_double),
+                ("rp_est", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("csr_cheaper", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -116,6 +119,7 @@ SIGNATURES = {
     "mhdc_stream_indirect": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp, _vp]),
     "mhdc_debug_fail_alloc": (ctypes.c_int, [_i32]),
     "mhdc_batch_create": (_vp, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
+    "mhdc_batch_create_rowmajor": (_vp, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
     "mhdc_batch_bind": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mhdc_batch_run": (ctypes.c_int, [_vp, _vp]),
     "mhdc_batch_graph_launch": (ctypes.c_int, [_vp, _vp]),
@@ -139,6 +143,8 @@ SIGNATURES = {
     "mhdc_mlp_destroy": (None, [_vp]),
     "mhdc_time_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
     "mhdc_select": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, ctypes.POINTER(SelectResult)]),
+    "mhdc_judge_keep": (ctypes.c_int, [_f64, _f64, _f64]),
+    "mhdc_refine_candidates": (_i32, [_f64, _i32, _vp, _vp, _i32]),
     "mhdc_select_refine": (_vp, [_i32, _vp, _vp, _vp, _vp, _f64, _vp,
                                  ctypes.POINTER(SelectResult)]),
 }
@@ -185,6 +191,13 @@ def _dptr(t, dtype, name):
 def _stream(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _rows_dense(t):
+    """The k values of each row of an (n, k) view are adjacent (stride 1 along
+    the row; any stride when k = 1) and rows are at least k apart."""
+    k = t.shape[1]
+    return (k == 1 or t.stride(1) == 1) and (t.shape[0] <= 1 or t.stride(0) >= k)
 
 
 class _Matrix:
@@ -250,13 +263,13 @@ class _Matrix:
         (n, ldx) with the k columns first (ldx >= k; a view X[:, :k] of a
         wider row-major array is allowed), Y likewise (allocated (n, k) when
         None)."""
-        if X.dim() != 2 or X.shape[0] != self.n or X.stride(1) != 1:
+        if X.dim() != 2 or X.shape[0] != self.n or not _rows_dense(X):
             raise ValueError("X must be an (n, k) row-major view")
         k = X.shape[1]
         ldx = X.stride(0) if self.n > 1 else k
         if Y is None:
             Y = torch.empty((self.n, k), dtype=torch.float64, device=X.device)
-        if tuple(Y.shape) != (self.n, k) or Y.stride(1) != 1:
+        if tuple(Y.shape) != (self.n, k) or not _rows_dense(Y):
             raise ValueError("Y must be an (%d, %d) row-major view" % (self.n, k))
         ldy = Y.stride(0) if self.n > 1 else k
         for t, name in ((X, "X"), (Y, "Y")):
@@ -411,34 +424,54 @@ def autotune(rowptr, colind, val, theta: float, nrhs: int = 1,
 class Batch:
     """Several M-HDC products Y_i = A_i X_i in one persistent launch.
 
-    mats: MHDCMatrix list; Xs: per item a (k_i, n_i) float64 device tensor
-    (rows are right-hand sides); Ys: outputs of the same shapes (allocated
-    when None).  The tensors must stay alive while the batch is used."""
+    mats: MHDCMatrix list; Xs: per item a float64 device tensor of shape
+    (k_i, n_i) (rows are right-hand sides; layout "colmajor") or (n_i, k_i)
+    (right-hand sides stored row by row; layout "rowmajor"); Ys: outputs of
+    the same shapes (allocated when None).  The tensors must stay alive
+    while the batch is used."""
 
-    def __init__(self, mats, Xs, Ys=None, wg_size=256):
+    def __init__(self, mats, Xs, Ys=None, wg_size=256, layout="colmajor"):
+        if layout not in ("colmajor", "rowmajor"):
+            raise ValueError("layout must be colmajor or rowmajor")
+        self.rowmajor = layout == "rowmajor"
         self.mats = list(mats)
         self.Xs = list(Xs)
         self.Ys = list(Ys) if Ys is not None else [torch.empty_like(X) for X in self.Xs]
         cnt = len(self.mats)
         hs = (ctypes.c_void_p * cnt)(*[m._h for m in self.mats])
-        k = (ctypes.c_int32 * cnt)(*[X.shape[0] for X in self.Xs])
+        k = (ctypes.c_int32 * cnt)(*[X.shape[1 if self.rowmajor else 0] for X in self.Xs])
         xp, yp, lx, ly = self._ptrs()
         torch.cuda.synchronize()
-        self._h = lib().mhdc_batch_create(cnt, hs, k, xp, lx, yp, ly, int(wg_size))
+        create = lib().mhdc_batch_create_rowmajor if self.rowmajor else lib().mhdc_batch_create
+        self._h = create(cnt, hs, k, xp, lx, yp, ly, int(wg_size))
         if not self._h:
             _raise()
 
     def _ptrs(self):
         cnt = len(self.mats)
         for m, X, Y in zip(self.mats, self.Xs, self.Ys):
-            if X.dim() != 2 or X.shape[1] != m.n or Y.shape != X.shape:
-                raise ValueError("X_i, Y_i must have shape (k_i, n_i)")
-            _dptr(X, torch.float64, "X")
-            _dptr(Y, torch.float64, "Y")
+            if self.rowmajor:
+                if (X.dim() != 2 or X.shape[0] != m.n or Y.shape != X.shape
+                        or not _rows_dense(X) or not _rows_dense(Y)):
+                    raise ValueError("X_i, Y_i must be (n_i, k_i) row-major views")
+                for t, name in ((X, "X"), (Y, "Y")):
+                    if t.dtype != torch.float64 or not t.is_cuda:
+                        raise ValueError("%s must be a float64 device tensor" % name)
+            else:
+                if X.dim() != 2 or X.shape[1] != m.n or Y.shape != X.shape:
+                    raise ValueError("X_i, Y_i must have shape (k_i, n_i)")
+                _dptr(X, torch.float64, "X")
+                _dptr(Y, torch.float64, "Y")
         xp = (ctypes.c_void_p * cnt)(*[X.data_ptr() for X in self.Xs])
         yp = (ctypes.c_void_p * cnt)(*[Y.data_ptr() for Y in self.Ys])
-        lx = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
-        ly = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
+        if self.rowmajor:
+            lx = (ctypes.c_int64 * cnt)(*[X.stride(0) if m.n > 1 else X.shape[1]
+                                          for m, X in zip(self.mats, self.Xs)])
+            ly = (ctypes.c_int64 * cnt)(*[Y.stride(0) if m.n > 1 else Y.shape[1]
+                                          for m, Y in zip(self.mats, self.Ys)])
+        else:
+            lx = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
+            ly = (ctypes.c_int64 * cnt)(*[m.n for m in self.mats])
         return xp, yp, lx, ly
 
     def bind(self, Xs, Ys):
@@ -629,3 +662,17 @@ def to_device(m, device="cuda"):
     """Copy a synth.CSRMatrix to device tensors (rowptr, colind, val)."""
     return (torch.from_numpy(m.rowptr).to(device), torch.from_numpy(m.colind).to(device),
             torch.from_numpy(m.val).to(device))
+
+
+def judge_keep(v_proposal, v_policy, tolerance):
+    """mhdc_judge_keep: the rule by which mhdc_select keeps a proposal."""
+    return bool(lib().mhdc_judge_keep(float(v_proposal), float(v_policy), float(tolerance)))
+
+
+def refine_candidates(theta, n_b):
+    """mhdc_refine_candidates: the (theta, n_b) pairs mhdc_select_refine
+    times besides the decision."""
+    th = (ctypes.c_double * 8)()
+    nb = (ctypes.c_int32 * 8)()
+    cnt = lib().mhdc_refine_candidates(float(theta), int(n_b), th, nb, 8)
+    return [(round(th[i], 1), int(nb[i])) for i in range(cnt)]

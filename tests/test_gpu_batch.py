@@ -67,6 +67,39 @@ def test_batch_run_matches_items(batch_case):
         b.close()
 
 
+def test_batch_rowmajor_matches_items(batch_case):
+    """Right-hand sides stored row by row: every item equals its own
+    mhdc_spmm_rowmajor launch and the oracle's Fig. 16 kernel bit for bit,
+    in a plain run and in a graph replay, for both workgroup sizes."""
+    items, mats, Xs, refs, _ = batch_case
+    Xr = [X.t().contiguous() for X in Xs]   # (n_i, k_i), row-major
+    for wg in (256, 64):
+        say("case: row-major batch wg=%d" % wg)
+        b = mhdc.Batch(mats, Xr, wg_size=wg, layout="rowmajor")
+        b.run()
+        torch.cuda.synchronize()
+        for (m, k, nb), mat, X, Y, ref in zip(items, mats, Xr, b.Ys, refs):
+            single = mat.spmm_rowmajor(X)
+            assert_same_bits(Y.cpu().numpy(), single.cpu().numpy(),
+                             "row-major item n=%d vs single launch" % m.n)
+            Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+            for r in range(k):
+                assert_oracle_bits(np.ascontiguousarray(Yh[:, r]),
+                                   oracle.mhdc_spmv(ref, np.ascontiguousarray(Xh[:, r])),
+                                   "row-major item n=%d rhs %d" % (m.n, r))
+        got = [Y.clone() for Y in b.Ys]
+        for Y in b.Ys:
+            Y.fill_(float("nan"))
+        stream = torch.cuda.Stream()
+        b.graph_launch(stream)
+        stream.synchronize()
+        for g, Y in zip(got, b.Ys):
+            assert_same_bits(g.cpu().numpy(), Y.cpu().numpy(), "row-major graph replay")
+        b.close()
+    with pytest.raises(ValueError):
+        mhdc.Batch(mats, Xs, layout="rowmajor")   # column-major shapes
+
+
 def test_batch_graph_replays(batch_case):
     """Replay the captured graph several times with eager work in between;
     every replay must equal the eager batch result for the current X."""

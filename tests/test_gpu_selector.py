@@ -152,6 +152,29 @@ def test_select_policy_network_and_judge():
     assert r["net_ok"] == 0 and r["used_rule"] == 1
 
 
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.9])
+def test_select_reports_the_csr_verdict(theta):
+    """The byte model's verdict on the chosen layout against plain CSR
+    (Sec. 5.3): rp_est = V_CSR / V of the chosen handle, its alpha and beta,
+    and csr_cheaper exactly when V_CSR < V, i.e. alpha < 2/3 (Eqs. 31-32),
+    the oracle model evaluated on the oracle converter's layout."""
+    from oracle import model
+    m = synth.random_csr(400, 21, density=0.01, bands=[0, 1, -1, 5, -9, 40], band_fill=0.62)
+    say("case: select verdict theta=%.1f" % theta)
+    d = dev(m)
+    net = _fixed_net(theta, 6.0)   # proposes (clip(theta, 0.5, 0.9), 64)
+    h, r = mhdc.select(*d, model=net, tolerance=1e9)
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, r["n_b"], r["theta"])
+    S_, R_ = ref.dia_val.size, ref.R
+    v = model.v_hdc_blocked(m.n, R_, S_)
+    v_csr = model.v_csr_general(m.n, m.nnz)
+    assert r["rp_est"] == v_csr / v
+    assert (r["alpha"], r["beta"]) == model.alpha_beta(m.nnz, R_, S_)
+    assert r["csr_cheaper"] == int(v_csr < v)
+    assert r["csr_cheaper"] == int(S_ > 0 and r["alpha"] < 2.0 / 3.0)
+    h.close()
+
+
 def test_select_refine_returns_a_timed_neighbour():
     """mhdc_select_refine returns mhdc_select's choice, one of its grid
     neighbours (n_b halved / doubled, theta -+ 0.1), the policy or the
