@@ -132,7 +132,7 @@ __global__ __launch_bounds__(WG) void k_batch_rm(const BatchItem *__restrict__ i
                                                  int32_t count, int64_t total_tiles,
                                                  int32_t *counter)
 {
-    __shared__ double s_prod[TileShapeRm<WG, 2>::LDS_BYTES / 8];
+    __shared__ double s_prod[(TileShapeRm<WG, 2>::LDS_BYTES + 7) / 8];
     static_assert(TileShapeRm<WG, 2>::LDS_BYTES == TileShapeRm<WG, 16>::LDS_BYTES,
                   "one LDS size for every width");
     __shared__ int64_t s_tile;

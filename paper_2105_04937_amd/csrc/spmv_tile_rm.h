@@ -23,8 +23,10 @@
 //   * CSR part: per chunk of the tile's entries, the wavefronts form the
 //     rounded products w * X[col*ldx + c] with lane (s, c) taking entries
 //     s, s + RPI, ... of its wavefront's share (independent gathers, RPI
-//     entries times KC columns per load) and store them in LDS; each lane
-//     then adds the products of its rows' entries in column order.
+//     entries times KC columns per load, eight in flight per lane) and
+//     store them in LDS; each lane then adds the products of its rows'
+//     entries in column order, finding them through the tile's row
+//     pointers, which are staged in LDS once per tile.
 #pragma once
 
 #include "spmv_tile.h"
@@ -35,9 +37,10 @@ template <int WG, int KC>
 struct TileShapeRm {
     static_assert(KC >= 2 && KC <= 16 && (KC & (KC - 1)) == 0, "2..16 columns");
     static constexpr int RPI = 64 / KC;
-    // remainder entries per chunk: 32 KB of products
+    // remainder entries per chunk: 32 KB of products, then the tile's
+    // WG + 1 remainder row pointers
     static constexpr int CH = 4096 / KC;
-    static constexpr int LDS_BYTES = CH * KC * 8;
+    static constexpr int LDS_BYTES = CH * KC * 8 + (WG + 1) * 4;
     static_assert(CH % (WG / 64 * RPI) == 0, "chunk splits evenly over the slots");
     // products per lane and chunk
     static constexpr int PER_LANE = CH / (WG / 64) / RPI;
@@ -82,11 +85,16 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
         const int32_t e_end = uniform_load(a.rem_ptr, tile_end);
         if (e_beg < e_end) {
             double *s_prod = static_cast<double *>(lds);
+            // the tile's row pointers, read once (each chunk looks them up)
+            int32_t *s_rp = reinterpret_cast<int32_t *>(s_prod + CH * KC);
+            for (int i = threadIdx.x; i <= WG; i += WG)
+                s_rp[i] = tile_base + i <= n ? a.rem_ptr[tile_base + i] : e_end;
             for (int32_t cb = e_beg; cb < e_end; cb += CH) {
                 const int32_t ce = cb + CH < e_end ? cb + CH : e_end;
-                // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W)
+                // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W);
+                // eight gathers in flight per lane
                 const int32_t wb = cb + wave * (CH / (WG / 64));
-#pragma unroll 4
+#pragma unroll 8
                 for (int j = 0; j < Sh::PER_LANE; j++) {
                     const int32_t e = wb + s + RPI * j;
                     if (e < ce) {
@@ -101,7 +109,8 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                 for (int q = 0; q < KC; q++) {
                     const int64_t row = wave_base + s + RPI * q;
                     if (row < n && col_live) {
-                        const int32_t rs = a.rem_ptr[row], re = a.rem_ptr[row + 1];
+                        const int r = (int)(row - tile_base);
+                        const int32_t rs = s_rp[r], re = s_rp[r + 1];
                         const int32_t lo = rs > cb ? rs : cb;
                         const int32_t hi = re < ce ? re : ce;
                         for (int32_t e = lo; e < hi; e++)
