@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.6)
     ap.add_argument("--layouts", default="colmajor,rowmajor")
+    ap.add_argument("--fixed-only", action="store_true",
+                    help="skip the autotuner: only the n_b = 256 handles (for counter runs)")
     args = ap.parse_args()
     layouts = args.layouts.split(",")
 
@@ -71,11 +73,14 @@ def main():
     for i in range(args.count):
         m, k = synth.batch_member(i)
         d = mhdc.to_device(m)
-        t0 = time.perf_counter()
-        h, res = mhdc.autotune(*d, args.theta, nrhs=k, nb_candidates=cands)
-        t_tune += time.perf_counter() - t0
-        tuned.append(h)
         fixed.append(mhdc.MHDCMatrix.from_csr(*d, 256, args.theta))
+        if args.fixed_only:
+            res = dict(n_b=256, launch=None)
+        else:
+            t0 = time.perf_counter()
+            h, res = mhdc.autotune(*d, args.theta, nrhs=k, nb_candidates=cands)
+            t_tune += time.perf_counter() - t0
+            tuned.append(h)
         X = np.random.default_rng([4000 + i, 2]).uniform(-1, 1, size=(k, m.n))
         Xs.append(torch.from_numpy(np.ascontiguousarray(X)).cuda())
         meta.append(dict(n=m.n, nnz=m.nnz, k=k, points=m.meta["points"], n_b=res["n_b"],
@@ -97,7 +102,7 @@ def main():
 
     res = {}
     runs = [(lab, mats, lay) for lay in layouts
-            for lab, mats in (("autotuned", tuned), ("n_b256", fixed))]
+            for lab, mats in (("autotuned", tuned), ("n_b256", fixed)) if mats]
     for label, mats, lay in runs:
         rowmajor = lay == "rowmajor"
         Xl = Xs_rm if rowmajor else Xs
@@ -127,7 +132,8 @@ def main():
             info["bytes_alg"] / t_graph / 1e9))
         b.close()
 
-    best = res["autotuned" if "colmajor" in layouts else "autotuned_rowmajor"]
+    best = res[("autotuned" if tuned else "n_b256") +
+               ("" if "colmajor" in layouts else "_rowmajor")]
     rec = {
         "metric": "batched M-HDC SpMM GFLOP/s (one persistent hipGraph launch), FP64, 1xMI355X",
         "value": best["gflops_graph"], "unit": "GFLOP/s", "n_gpus": 1,
