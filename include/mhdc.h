@@ -158,7 +158,12 @@ int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
  * (i, r) of X at X[i*ldx + r] (ldx >= k), likewise Y with ldy >= k.  Same
  * bits in every column as mhdc_spmm.  Each remainder entry reads one row of
  * X (k contiguous doubles) and each diagonal a contiguous span of rows,
- * where column-major X costs one cache line per column.  Asynchronous. */
+ * where column-major X costs one cache line per column.  The handle's
+ * csr_mode (mhdc_launch) picks the CSR-part variant: 1 = staged products
+ * (independent gathers; scattered columns), 2 = staged values and columns
+ * with each lane gathering for its own rows (rows that repeat their
+ * neighbours' offsets, such as stencils), 0 = 2 when row_repeat >= 0.5,
+ * else 1.  rows_per_lane and rhs_group do not apply.  Asynchronous. */
 int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y,
                        int64_t ldy, int32_t k, hipStream_t stream);
 

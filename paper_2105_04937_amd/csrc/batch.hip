@@ -75,7 +75,10 @@ __device__ inline void batch_tile(const BatchItem &it, int64_t local, double *ld
 template <int WG, int KC>
 __device__ inline void batch_tile_rm(const BatchItem &it, int64_t local, double *lds)
 {
-    spmv_tile_rm<WG, KC, true, true>(it.a, local, lds);
+    if (it.rg)
+        spmv_tile_rm<WG, KC, true, true, true>(it.a, local, lds);
+    else
+        spmv_tile_rm<WG, KC, true, true, false>(it.a, local, lds);
 }
 
 __global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
@@ -227,7 +230,7 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
         BatchItem &it = items[i];
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
         it.kc = b->rowmajor ? rm_columns(k) : kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
-        it.rg = row_gather(m.launch.csr_mode, it.kc) ? 1 : 0;
+        it.rg = (b->rowmajor ? rm_row_gather(m) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
         it.tile_begin = tiles;
         tiles += ((int64_t)m.n + wg - 1) / wg;
         flops += 2.0 * (double)m.nnz * k;

@@ -10,21 +10,25 @@ namespace {
 using KernelFn = void (*)(SpmvArgs);
 
 // Row-major right-hand sides: one tile of WG rows per workgroup.
-template <int WG, int KC, bool HAS_DIA, bool HAS_REM>
+template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
 __global__ __launch_bounds__(WG) void k_spmm_rm(SpmvArgs a)
 {
     __shared__ double s_lds[HAS_REM ? (TileShapeRm<WG, KC>::LDS_BYTES + 7) / 8 : 1];
     const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x, a.remap) : (int)blockIdx.x;
-    spmv_tile_rm<WG, KC, HAS_DIA, HAS_REM>(a, tile, s_lds);
+    spmv_tile_rm<WG, KC, HAS_DIA, HAS_REM, RG>(a, tile, s_lds);
 }
 
+// parts: 1 = DIA part, 2 = CSR part, 4 = CSR part by row gathers
 template <int WG, int KC>
 KernelFn pick_rm_parts(int parts)
 {
-    switch (parts & 3) {
-    case 1: return (KernelFn)k_spmm_rm<WG, KC, true, false>;
-    case 2: return (KernelFn)k_spmm_rm<WG, KC, false, true>;
-    case 3: return (KernelFn)k_spmm_rm<WG, KC, true, true>;
+    switch (parts) {
+    case 1:
+    case 5: return (KernelFn)k_spmm_rm<WG, KC, true, false, false>;
+    case 2: return (KernelFn)k_spmm_rm<WG, KC, false, true, false>;
+    case 3: return (KernelFn)k_spmm_rm<WG, KC, true, true, false>;
+    case 6: return (KernelFn)k_spmm_rm<WG, KC, false, true, true>;
+    case 7: return (KernelFn)k_spmm_rm<WG, KC, true, true, true>;
     }
     return nullptr;
 }
@@ -80,6 +84,13 @@ int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const do
     return MHDC_OK;
 }
 
+bool rm_row_gather(const BdcMatrix &m)
+{
+    if (m.launch.csr_mode == 0)
+        return m.row_repeat >= 0.5;
+    return m.launch.csr_mode == 2;
+}
+
 int rm_columns(int32_t k)
 {
     const int kc = kc_for(k);
@@ -100,7 +111,8 @@ int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
         k_zero_rows<<<dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, stream>>>(Y, ldy,
                                                                                       m.n, k);
     } else {
-        KernelFn fn = pick_rm(wg, rm_columns(k), (has_dia ? 1 : 0) | (has_rem ? 2 : 0));
+        KernelFn fn = pick_rm(wg, rm_columns(k), (has_dia ? 1 : 0) | (has_rem ? 2 : 0) |
+                                                     (rm_row_gather(m) ? 4 : 0));
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, 1);

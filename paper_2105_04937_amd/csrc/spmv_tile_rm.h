@@ -37,10 +37,13 @@ template <int WG, int KC>
 struct TileShapeRm {
     static_assert(KC >= 2 && KC <= 16 && (KC & (KC - 1)) == 0, "2..16 columns");
     static constexpr int RPI = 64 / KC;
-    // remainder entries per chunk: 32 KB of products, then the tile's
-    // WG + 1 remainder row pointers
+    // remainder entries per chunk: 32 KB of products (staged products), or
+    // 8 entries per lane of values and columns (row gathers); then the
+    // tile's WG + 1 remainder row pointers
     static constexpr int CH = 4096 / KC;
-    static constexpr int LDS_BYTES = CH * KC * 8 + (WG + 1) * 4;
+    static constexpr int CHR = WG * 8;
+    static constexpr int STAGE_BYTES = CH * KC * 8 > CHR * 12 ? CH * KC * 8 : CHR * 12;
+    static constexpr int LDS_BYTES = STAGE_BYTES + (WG + 1) * 4;
     static_assert(CH % (WG / 64 * RPI) == 0, "chunk splits evenly over the slots");
     // products per lane and chunk
     static constexpr int PER_LANE = CH / (WG / 64) / RPI;
@@ -48,7 +51,11 @@ struct TileShapeRm {
     static constexpr int U = KC >= 8 ? 1 : 2;
 };
 
-template <int WG, int KC, bool HAS_DIA, bool HAS_REM>
+// RG: the CSR part's values and columns are staged and each lane gathers X
+// for its own rows' entries (rows of similar structure, such as stencils,
+// then read neighbouring rows of X in one load); otherwise the rounded
+// products are staged (independent gathers, best for scattered columns).
+template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
 __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
 {
     // products are rounded before they are added: no multiply-add fusion
@@ -86,38 +93,78 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
         if (e_beg < e_end) {
             double *s_prod = static_cast<double *>(lds);
             // the tile's row pointers, read once (each chunk looks them up)
-            int32_t *s_rp = reinterpret_cast<int32_t *>(s_prod + CH * KC);
+            int32_t *s_rp = reinterpret_cast<int32_t *>(static_cast<char *>(lds) + Sh::STAGE_BYTES);
             for (int i = threadIdx.x; i <= WG; i += WG)
                 s_rp[i] = tile_base + i <= n ? a.rem_ptr[tile_base + i] : e_end;
-            for (int32_t cb = e_beg; cb < e_end; cb += CH) {
-                const int32_t ce = cb + CH < e_end ? cb + CH : e_end;
-                // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W);
-                // eight gathers in flight per lane
-                const int32_t wb = cb + wave * (CH / (WG / 64));
-#pragma unroll 8
-                for (int j = 0; j < Sh::PER_LANE; j++) {
-                    const int32_t e = wb + s + RPI * j;
-                    if (e < ce) {
-                        const double w = __builtin_nontemporal_load(a.rem_val + e);
-                        const int32_t col = __builtin_nontemporal_load(a.rem_col + e);
-                        const double xv = col_live ? X[(int64_t)col * ldx + c] : 0.0;
-                        s_prod[(e - cb) * KC + c] = __dmul_rn(w, xv);
-                    }
-                }
-                __syncthreads();
+            if constexpr (RG) {
+                constexpr int CHR = Sh::CHR;
+                double *s_val = s_prod;
+                int32_t *s_col = reinterpret_cast<int32_t *>(s_val + CHR);
+                for (int32_t cb = e_beg; cb < e_end; cb += CHR) {
+                    const int32_t ce = cb + CHR < e_end ? cb + CHR : e_end;
 #pragma unroll
-                for (int q = 0; q < KC; q++) {
-                    const int64_t row = wave_base + s + RPI * q;
-                    if (row < n && col_live) {
-                        const int r = (int)(row - tile_base);
-                        const int32_t rs = s_rp[r], re = s_rp[r + 1];
-                        const int32_t lo = rs > cb ? rs : cb;
-                        const int32_t hi = re < ce ? re : ce;
-                        for (int32_t e = lo; e < hi; e++)
-                            acc[q] = __dadd_rn(acc[q], s_prod[(e - cb) * KC + c]);
+                    for (int j = 0; j < CHR / WG; j++) {
+                        const int32_t e = cb + j * WG + (int32_t)threadIdx.x;
+                        if (e < ce) {
+                            s_val[e - cb] = __builtin_nontemporal_load(a.rem_val + e);
+                            s_col[e - cb] = __builtin_nontemporal_load(a.rem_col + e);
+                        }
                     }
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < KC; q++) {
+                        const int64_t row = wave_base + s + RPI * q;
+                        if (row < n && col_live) {
+                            const int r = (int)(row - tile_base);
+                            const int32_t rs = s_rp[r], re = s_rp[r + 1];
+                            const int32_t lo = rs > cb ? rs : cb;
+                            const int32_t hi = re < ce ? re : ce;
+                            int32_t e = lo;
+                            for (; e + 2 <= hi; e += 2) {
+                                const double w0 = s_val[e - cb], w1 = s_val[e + 1 - cb];
+                                const double x0 = X[(int64_t)s_col[e - cb] * ldx + c];
+                                const double x1 = X[(int64_t)s_col[e + 1 - cb] * ldx + c];
+                                acc[q] = __dadd_rn(acc[q], __dmul_rn(w0, x0));
+                                acc[q] = __dadd_rn(acc[q], __dmul_rn(w1, x1));
+                            }
+                            if (e < hi)
+                                acc[q] = __dadd_rn(acc[q], __dmul_rn(s_val[e - cb],
+                                                                     X[(int64_t)s_col[e - cb] * ldx + c]));
+                        }
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
+            } else {
+                for (int32_t cb = e_beg; cb < e_end; cb += CH) {
+                    const int32_t ce = cb + CH < e_end ? cb + CH : e_end;
+                    // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W);
+                    // eight gathers in flight per lane
+                    const int32_t wb = cb + wave * (CH / (WG / 64));
+#pragma unroll 8
+                    for (int j = 0; j < Sh::PER_LANE; j++) {
+                        const int32_t e = wb + s + RPI * j;
+                        if (e < ce) {
+                            const double w = __builtin_nontemporal_load(a.rem_val + e);
+                            const int32_t col = __builtin_nontemporal_load(a.rem_col + e);
+                            const double xv = col_live ? X[(int64_t)col * ldx + c] : 0.0;
+                            s_prod[(e - cb) * KC + c] = __dmul_rn(w, xv);
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < KC; q++) {
+                        const int64_t row = wave_base + s + RPI * q;
+                        if (row < n && col_live) {
+                            const int r = (int)(row - tile_base);
+                            const int32_t rs = s_rp[r], re = s_rp[r + 1];
+                            const int32_t lo = rs > cb ? rs : cb;
+                            const int32_t hi = re < ce ? re : ce;
+                            for (int32_t e = lo; e < hi; e++)
+                                acc[q] = __dadd_rn(acc[q], s_prod[(e - cb) * KC + c]);
+                        }
+                    }
+                    __syncthreads();
+                }
             }
         }
     }

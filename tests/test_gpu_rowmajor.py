@@ -53,10 +53,10 @@ def test_rowmajor_matches_oracle(i):
         X = rng.uniform(-1, 1, size=(m.n, k))
         Xd = _rm(X)
         for name, h, f in mats:
-            for wg in (64, 256):
-                h.set_launch(1, wg, 0 if wg == 64 else 16)
+            for wg, mode in ((64, 1), (256, 2), (256, 1), (64, 0)):
+                h.set_launch(1, wg, 0 if wg == 64 else 16, mode)
                 Y = h.spmm_rowmajor(Xd)
-                _check_cols(Y, want_for(f, X, k), "%s wg %d" % (name, wg))
+                _check_cols(Y, want_for(f, X, k), "%s wg %d csr_mode %d" % (name, wg, mode))
             Yc = h.spmm(_rm(X.T))  # column-major product of the same columns
             assert_same_bits(Yc.cpu().numpy().T, Y.cpu().numpy(), "%s row- vs column-major" % name)
     for _, h, _ in mats:
@@ -77,11 +77,13 @@ def test_rowmajor_padded_leading_dimensions():
     k = 5
     Xw = rng.uniform(-1, 1, size=(m.n, 24))
     Xd = _rm(Xw)[:, :k]
-    Yw = torch.full((m.n, 20), float("nan"), dtype=torch.float64, device="cuda")
-    h.spmm_rowmajor(Xd, Yw[:, :k])
-    _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
-                            for r in range(k)], "padded")
-    assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
+    for mode in (1, 2):
+        h.set_launch(1, 256, 16, mode)
+        Yw = torch.full((m.n, 20), float("nan"), dtype=torch.float64, device="cuda")
+        h.spmm_rowmajor(Xd, Yw[:, :k])
+        _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
+                                for r in range(k)], "padded, csr_mode %d" % mode)
+        assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
     # argument checks: ld below k, overlapping X and Y
     buf = torch.zeros((m.n, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(mhdc.MhdcError) as e:
