@@ -10,7 +10,11 @@ everything the GPU side computes for it:
 * features: a census of partial diagonals at probe block size 256 (the same
   count N~(d, ib) as Sec. 4.3) summarised per offset bin;
 * a 66 -> 128 -> 128 -> 2 multilayer perceptron with ReLU hidden layers,
-  its squared-error loss, the gradient by backpropagation, and Adam.
+  its squared-error loss, the gradient by backpropagation, and Adam;
+* the grid loss: the network's output read as a point of the (theta,
+  log2 n_b) grid on which the paper sweeps its parameters (Sec. 6.4.1),
+  scored by the measured time there, interpolated bilinearly between the
+  grid points.
 
 Only tests import this module.
 """
@@ -125,13 +129,64 @@ def forward(p, X):
 
 def loss_and_grad(p, X, T, w=(1.0, 1.0)):
     """L = sum_b sum_o w_o (out_bo - T_bo)^2 / B and dL/dp by backpropagation."""
-    W1, b1, W2, b2, W3, b3 = unpack(p)
-    out, (X, a1, h1, a2, h2) = forward(p, X)
-    B = X.shape[0]
+    out, cache = forward(p, X)
+    B = cache[0].shape[0]
     w = np.asarray(w, np.float64)
     diff = out - np.asarray(T, np.float64)
     L = float(np.sum(w * diff * diff) / B)
     d_out = 2.0 * w * diff / B
+    return L, backward(p, cache, d_out)
+
+
+# the grid of Sec. 6.4.1: theta in 0.5 .. 0.9 (step 0.1), n_b = 2^5 .. 2^12
+GRID_TH, GRID_NB = 5, 8
+
+
+def grid_value(G, o):
+    """Loss of outputs o[B][2] = (theta, log2 n_b) on grids G[B][5][8]
+    (G[r][i][j]: the measured log time ratio of matrix r at theta = 0.5 +
+    0.1 i, n_b = 2^(5+j)).  Inside the grid's box the value is the bilinear
+    interpolation of the four surrounding points; the cell of a point on an
+    inner grid line is the one above it (i = min(floor(u), 3),
+    j = min(floor(v), 6)).  Outside, the value at the clamped point plus the
+    distance to the box in output units (|theta - clamp| + |log2 n_b -
+    clamp|).  Returns (value[B], d value / d o [B][2])."""
+    G = np.asarray(G, np.float64).reshape(-1, GRID_TH, GRID_NB)
+    o = np.asarray(o, np.float64)
+    t = np.clip(o[:, 0], 0.5, 0.9)
+    l = np.clip(o[:, 1], 5.0, 12.0)
+    u = (t - 0.5) / 0.1
+    v = l - 5.0
+    i = np.minimum(np.floor(u), GRID_TH - 2).astype(np.int64)
+    j = np.minimum(np.floor(v), GRID_NB - 2).astype(np.int64)
+    fu, fv = u - i, v - j
+    r = np.arange(o.shape[0])
+    g00, g10 = G[r, i, j], G[r, i + 1, j]
+    g01, g11 = G[r, i, j + 1], G[r, i + 1, j + 1]
+    val = ((1 - fu) * (1 - fv) * g00 + fu * (1 - fv) * g10 + (1 - fu) * fv * g01
+           + fu * fv * g11)
+    du = (1 - fv) * (g10 - g00) + fv * (g11 - g01)
+    dv = (1 - fu) * (g01 - g00) + fu * (g11 - g10)
+    inside_t = (o[:, 0] >= 0.5) & (o[:, 0] <= 0.9)
+    inside_l = (o[:, 1] >= 5.0) & (o[:, 1] <= 12.0)
+    d0 = np.where(inside_t, du / 0.1, np.where(o[:, 0] < 0.5, -1.0, 1.0))
+    d1 = np.where(inside_l, dv, np.where(o[:, 1] < 5.0, -1.0, 1.0))
+    val = val + np.abs(o[:, 0] - t) + np.abs(o[:, 1] - l)
+    return val, np.stack([d0, d1], axis=1)
+
+
+def grid_loss_and_grad(p, X, G):
+    """L = sum_b grid_value(G_b, out_b) / B and dL/dp by backpropagation."""
+    out, cache = forward(p, X)
+    B = cache[0].shape[0]
+    val, d = grid_value(G, out)
+    return float(np.sum(val) / B), backward(p, cache, d / B)
+
+
+def backward(p, cache, d_out):
+    """dL/dp for dL/d(out) = d_out through the network of forward()."""
+    W1, b1, W2, b2, W3, b3 = unpack(p)
+    X, a1, h1, a2, h2 = cache
     gW3 = d_out.T @ h2
     gb3 = d_out.sum(axis=0)
     d_h2 = d_out @ W3
@@ -142,7 +197,7 @@ def loss_and_grad(p, X, T, w=(1.0, 1.0)):
     d_a1 = d_h1 * (a1 > 0)
     gW1 = d_a1.T @ X
     gb1 = d_a1.sum(axis=0)
-    return L, pack([gW1, gb1, gW2, gb2, gW3, gb3])
+    return pack([gW1, gb1, gW2, gb2, gW3, gb3])
 
 
 def adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

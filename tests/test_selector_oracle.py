@@ -96,3 +96,70 @@ def test_adam_first_step_closed_form():
 def test_decode():
     th, nb = S.decode([[0.3, 4.2], [0.72, 7.6], [1.5, 20.0], [0.649, 8.5]])
     assert list(th) == [0.5, 0.7, 0.9, 0.6] and list(nb) == [32, 256, 4096, 256]
+
+
+# ------------------------------------------------------------ grid loss
+def _grid(rng, B):
+    return rng.uniform(0.0, 0.5, size=(B, S.GRID_TH, S.GRID_NB))
+
+
+def test_grid_value_at_nodes_and_outside():
+    """At a grid point the value is that point's entry; outside the box it
+    is the clamped point's value plus the distance in output units, with
+    slope -1 / +1 pointing back into the box."""
+    rng = np.random.default_rng(3)
+    G = _grid(rng, 1)
+    for i in range(S.GRID_TH):
+        for j in range(S.GRID_NB):
+            v, _ = S.grid_value(G, [[0.5 + 0.1 * i, 5.0 + j]])
+            assert abs(v[0] - G[0, i, j]) <= 1e-12
+    v, d = S.grid_value(G, [[0.3, 13.5]])
+    assert abs(v[0] - (G[0, 0, 7] + 0.2 + 1.5)) <= 1e-12
+    assert list(d[0]) == [-1.0, 1.0]
+    v, d = S.grid_value(G, [[1.2, 2.0]])
+    assert abs(v[0] - (G[0, 4, 0] + 0.3 + 3.0)) <= 1e-12
+    assert list(d[0]) == [1.0, -1.0]
+
+
+def test_grid_value_affine_closed_form():
+    """On an affine grid G[i][j] = a i + b j + c the bilinear value is
+    exactly affine: a u + b v + c with u = (theta - 0.5)/0.1, v = log2 n_b
+    - 5, and the output gradient is (a / 0.1, b)."""
+    rng = np.random.default_rng(4)
+    a, b, c = 0.07, -0.03, 0.2
+    ii, jj = np.meshgrid(np.arange(S.GRID_TH), np.arange(S.GRID_NB), indexing="ij")
+    G = np.broadcast_to(a * ii + b * jj + c, (9, S.GRID_TH, S.GRID_NB))
+    o = np.stack([rng.uniform(0.51, 0.89, 9), rng.uniform(5.1, 11.9, 9)], axis=1)
+    v, d = S.grid_value(G, o)
+    want = a * (o[:, 0] - 0.5) / 0.1 + b * (o[:, 1] - 5.0) + c
+    assert np.allclose(v, want, rtol=0, atol=1e-12)
+    assert np.allclose(d, [[a / 0.1, b]] * 9, rtol=0, atol=1e-12)
+
+
+def test_grid_backprop_matches_finite_differences():
+    """dL/dp of the grid loss against central differences in FP64, at
+    parameters whose outputs lie inside grid cells (away from the kinks on
+    the grid lines, where the loss has no derivative)."""
+    rng = np.random.default_rng(5)
+    p = S.init_params(6).astype(np.float64) * 0.5
+    X = rng.uniform(0, 1, size=(6, S.N_IN))
+    # place the outputs inside cells through the output bias
+    out, _ = S.forward(p, X)
+    p[-2] += 0.645 - out[:, 0].mean()
+    p[-1] += 8.45 - out[:, 1].mean()
+    out, _ = S.forward(p, X)
+    u, v = (out[:, 0] - 0.5) / 0.1, out[:, 1] - 5.0
+    assert np.all(np.abs(u - np.round(u)) > 1e-3) and np.all(np.abs(v - np.round(v)) > 1e-3)
+    assert np.all((out[:, 0] > 0.5) & (out[:, 0] < 0.9) & (out[:, 1] > 5) & (out[:, 1] < 12))
+    G = _grid(rng, 6)
+    L, g = S.grid_loss_and_grad(p, X, G)
+    idx = np.concatenate([rng.choice(S.N_PARAMS, size=200, replace=False),
+                          [S.N_PARAMS - 1, S.N_PARAMS - 2, S.N_PARAMS - 130, 0]])
+    h = 1e-7
+    for i in idx:
+        e = np.zeros(S.N_PARAMS)
+        e[i] = h
+        Lp, _ = S.grid_loss_and_grad(p + e, X, G)
+        Lm, _ = S.grid_loss_and_grad(p - e, X, G)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-5 * max(1.0, abs(fd)), (i, fd, g[i])
