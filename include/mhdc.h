@@ -389,6 +389,23 @@ int mhdc_mlp_loss_grad(mhdc_mlp m, const float *X, const float *T, int32_t B,
 int mhdc_mlp_train(mhdc_mlp m, const float *X, const float *T, int32_t N,
                    const int32_t *order, int64_t steps, int32_t B, float lr,
                    float w0, float w1, float *loss_hist, hipStream_t stream);
+/* Grid loss (not in the paper; it scores a proposal by what the paper's
+ * sweep of Sec. 6.4.1 measures): G[B][40] holds per row the measured log
+ * time ratios log(t / t_best) at theta = 0.5 + 0.1 i (i < 5), n_b =
+ * 2^(5+j) (j < 8), at G[r][8 i + j].  Output o_r = (theta, log2 n_b) is
+ * scored by the bilinear interpolation of the four grid values around it
+ * (the cell above a point on an inner grid line), and outside the grid's
+ * box by the value at the clamped point plus |theta - clamp| + |log2 n_b -
+ * clamp|; loss = sum_r score_r / B and its gradient (MHDC_MLP_PARAMS
+ * floats).  Device arrays; asynchronous on stream. */
+int mhdc_mlp_grid_loss_grad(mhdc_mlp m, const float *X, const float *G, int32_t B,
+                            float *loss, float *grad, hipStream_t stream);
+/* As mhdc_mlp_train with the grid loss: G[N][40] as above replaces the
+ * targets.  The Adam state and step count carry over from earlier training
+ * calls on the network.  Synchronous. */
+int mhdc_mlp_train_grid(mhdc_mlp m, const float *X, const float *G, int32_t N,
+                        const int32_t *order, int64_t steps, int32_t B, float lr,
+                        float *loss_hist, hipStream_t stream);
 /* Decisions for B feature rows: theta[r] = round(10 clip(o_r0, 0.5, 0.9))/10
  * (the theta grid of Sec. 6.4.1), n_b[r] = 2^clip(round(o_r1), 5, 12),
  * ok[r] = 0 (and the policy 0.6 / 256) for a non-finite output.  Device

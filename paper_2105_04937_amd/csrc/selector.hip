@@ -35,6 +35,9 @@ namespace mhdc {
 namespace {
 
 constexpr int N_BINS = 64, N_IN = 66, HID = 128, N_OUT = 2, PROBE_NB = 256;
+// the (theta, log2 n_b) sweep grid of the grid loss: theta = 0.5 + 0.1 i
+// (i < 5), n_b = 2^(5 + j) (j < 8)
+constexpr int GRID_TH = 5, GRID_NB = 8, N_GRID = GRID_TH * GRID_NB;
 constexpr int P_W1 = 0;
 constexpr int P_B1 = P_W1 + HID * N_IN;
 constexpr int P_W2 = P_B1 + HID;
@@ -239,22 +242,68 @@ __global__ __launch_bounds__(TW) void k_check_order(const int32_t *__restrict__ 
             *bad = 1;
 }
 
-// rows order[local_step*B + r] of X/T -> minibatch buffers
+// rows order[local_step*B + r] of X and of the targets T (tdim values per
+// row: N_OUT target outputs, or N_GRID grid values) -> minibatch buffers
 __global__ __launch_bounds__(TW) void k_gather(const float *__restrict__ X,
-                                               const float *__restrict__ T,
+                                               const float *__restrict__ T, int tdim,
                                                const int32_t *__restrict__ order,
                                                const int32_t *local_step, int B,
                                                float *__restrict__ Xb, float *__restrict__ Tb)
 {
     const int idx = blockIdx.x * TW + threadIdx.x;
-    if (idx >= B * (N_IN + N_OUT))
+    if (idx >= B * (N_IN + tdim))
         return;
-    const int r = idx / (N_IN + N_OUT), c = idx - r * (N_IN + N_OUT);
+    const int r = idx / (N_IN + tdim), c = idx - r * (N_IN + tdim);
     const int64_t src = order[(int64_t)(*local_step) * B + r];
     if (c < N_IN)
         Xb[(int64_t)r * N_IN + c] = X[src * N_IN + c];
     else
-        Tb[(int64_t)r * N_OUT + (c - N_IN)] = T[src * N_OUT + (c - N_IN)];
+        Tb[(int64_t)r * tdim + (c - N_IN)] = T[src * tdim + (c - N_IN)];
+}
+
+// Grid loss: each output row o = (theta, log2 n_b) read as a point of the
+// sweep grid and scored by the grid values G (the measured log time ratios)
+// interpolated bilinearly from the four surrounding points; outside the
+// grid's box the value at the clamped point plus the distance to the box.
+// loss = sum_r value_r / B (fixed-order tree), d_out = d value / d o / B.
+// One workgroup.
+__global__ __launch_bounds__(TW) void k_grid_loss_grad(const float *__restrict__ out,
+                                                       const float *__restrict__ G, int B,
+                                                       float *__restrict__ d_out,
+                                                       float *loss_at, const int32_t *local_step)
+{
+    __shared__ float part[TW];
+    float acc = 0.0f;
+    for (int r = threadIdx.x; r < B; r += TW) {
+        const float o0 = out[2 * r], o1 = out[2 * r + 1];
+        const float t = fminf(fmaxf(o0, 0.5f), 0.9f), l = fminf(fmaxf(o1, 5.0f), 12.0f);
+        const float u = (t - 0.5f) / 0.1f, v = l - 5.0f;
+        const int i = min((int)floorf(u), GRID_TH - 2), j = min((int)floorf(v), GRID_NB - 2);
+        const float fu = u - (float)i, fv = v - (float)j;
+        const float *g = G + (int64_t)r * N_GRID;
+        const float g00 = g[i * GRID_NB + j], g10 = g[(i + 1) * GRID_NB + j];
+        const float g01 = g[i * GRID_NB + j + 1], g11 = g[(i + 1) * GRID_NB + j + 1];
+        const float val = (1.0f - fu) * (1.0f - fv) * g00 + fu * (1.0f - fv) * g10 +
+                          (1.0f - fu) * fv * g01 + fu * fv * g11;
+        const float du = (1.0f - fv) * (g10 - g00) + fv * (g11 - g01);
+        const float dv = (1.0f - fu) * (g01 - g00) + fu * (g11 - g10);
+        const float d0 = o0 < 0.5f ? -1.0f : (o0 > 0.9f ? 1.0f : du / 0.1f);
+        const float d1 = o1 < 5.0f ? -1.0f : (o1 > 12.0f ? 1.0f : dv);
+        d_out[2 * r] = d0 / (float)B;
+        d_out[2 * r + 1] = d1 / (float)B;
+        acc += val + fabsf(o0 - t) + fabsf(o1 - l);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = TW / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float *dst = loss_at + (local_step ? *local_step : 0);
+        *dst = part[0] / (float)B;
+    }
 }
 
 // (theta, n_b) from each network output row: theta = round(10 clip(o0, .5,
@@ -357,7 +406,7 @@ int ensure_buffers(mhdc_mlp_s *M, int32_t B)
     int rc;
     const size_t f = sizeof(float);
     if ((rc = dmalloc((void **)&M->Xb, f * B * N_IN, "mlp Xb")) ||
-        (rc = dmalloc((void **)&M->Tb, f * B * N_OUT, "mlp Tb")) ||
+        (rc = dmalloc((void **)&M->Tb, f * B * N_GRID, "mlp Tb")) ||
         (rc = dmalloc((void **)&M->h1, f * B * HID, "mlp h1")) ||
         (rc = dmalloc((void **)&M->h2, f * B * HID, "mlp h2")) ||
         (rc = dmalloc((void **)&M->out, f * B * N_OUT, "mlp out")) ||
@@ -551,11 +600,17 @@ int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, fl
     return launch_ok("mlp loss/grad");
 }
 
-int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const int32_t *order,
-                   int64_t steps, int32_t B, float lr, float w0, float w1, float *loss_hist,
-                   hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// Training shared by the two losses: grid = false, T holds N_OUT target
+// outputs per row and the loss is the weighted squared error; grid = true,
+// T holds the N_GRID grid values per row and the loss is the grid loss.
+int train_impl(mhdc_mlp M, const float *X, const float *T, int32_t N, const int32_t *order,
+               int64_t steps, int32_t B, float lr, float w0, float w1, float *loss_hist,
+               hipStream_t stream, bool grid)
 {
-    clear_error();
     if (!M || !X || !T || !order || !loss_hist || N < 1 || B < 1 || steps < 1)
         return set_error(MHDC_ERR_INVALID_ARG, "bad training arguments");
     if (steps * (int64_t)B > INT32_MAX)
@@ -594,9 +649,16 @@ int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const 
     if (e == hipSuccess)
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        k_gather<<<blocks_for(B * (N_IN + N_OUT)), TW, 0, cs>>>(X, T, order, M->local_step, B, M->Xb, M->Tb);
+        const int tdim = grid ? N_GRID : N_OUT;
+        k_gather<<<blocks_for(B * (N_IN + tdim)), TW, 0, cs>>>(X, T, tdim, order, M->local_step, B,
+                                                              M->Xb, M->Tb);
         enqueue_forward(M, M->Xb, B, cs);
-        k_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, w0, w1, M->d_out, loss_hist, M->local_step);
+        if (grid)
+            k_grid_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, M->d_out, loss_hist,
+                                               M->local_step);
+        else
+            k_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, w0, w1, M->d_out, loss_hist,
+                                          M->local_step);
         enqueue_backward(M, M->Xb, B, cs);
         k_adam<<<blocks_for(N_PARAMS), TW, 0, cs>>>(M->p, M->g, M->m, M->v, N_PARAMS, lr, 0.9f, 0.999f, 1e-8f, M->step);
         k_steps_inc<<<1, 1, 0, cs>>>(M->step, M->local_step);
@@ -618,6 +680,44 @@ int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const 
     if (e != hipSuccess)
         return set_error(MHDC_ERR_HIP, std::string("mlp train: ") + hipGetErrorString(e));
     return MHDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhdc_mlp_train(mhdc_mlp M, const float *X, const float *T, int32_t N, const int32_t *order,
+                   int64_t steps, int32_t B, float lr, float w0, float w1, float *loss_hist,
+                   hipStream_t stream)
+{
+    clear_error();
+    return train_impl(M, X, T, N, order, steps, B, lr, w0, w1, loss_hist, stream, false);
+}
+
+int mhdc_mlp_train_grid(mhdc_mlp M, const float *X, const float *G, int32_t N,
+                        const int32_t *order, int64_t steps, int32_t B, float lr,
+                        float *loss_hist, hipStream_t stream)
+{
+    clear_error();
+    return train_impl(M, X, G, N, order, steps, B, lr, 0.0f, 0.0f, loss_hist, stream, true);
+}
+
+int mhdc_mlp_grid_loss_grad(mhdc_mlp M, const float *X, const float *G, int32_t B, float *loss,
+                            float *grad, hipStream_t stream)
+{
+    clear_error();
+    if (!M || !X || !G || !loss || !grad || B < 1)
+        return set_error(MHDC_ERR_INVALID_ARG, "network, X, G, loss, grad and B >= 1 required");
+    MHDC_HIP_CHECK(hipStreamSynchronize(stream));
+    int rc = ensure_buffers(M, B);
+    if (rc)
+        return rc;
+    enqueue_forward(M, X, B, stream);
+    k_grid_loss_grad<<<1, TW, 0, stream>>>(M->out, G, B, M->d_out, loss, nullptr);
+    enqueue_backward(M, X, B, stream);
+    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice,
+                                  stream));
+    return launch_ok("mlp grid loss/grad");
 }
 
 int mhdc_mlp_decide(mhdc_mlp M, const float *X, int32_t B, double *theta, int32_t *n_b,

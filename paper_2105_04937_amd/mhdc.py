@@ -77,6 +77,7 @@ class SelectResult(ctypes.Structure):
 
 MLP_PARAMS = 25346
 MLP_IN = 66
+GRID_POINTS = 40  # theta 0.5 .. 0.9 x n_b 32 .. 4096
 
 
 _lib = None
@@ -139,6 +140,9 @@ SIGNATURES = {
                                           _vp, _vp, _vp]),
     "mhdc_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i64, _i32, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, _vp, _vp]),
+    "mhdc_mlp_grid_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "mhdc_mlp_train_grid": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _i64, _i32,
+                                           ctypes.c_float, _vp, _vp]),
     "mhdc_mlp_decide": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "mhdc_mlp_destroy": (None, [_vp]),
     "mhdc_time_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
@@ -589,6 +593,35 @@ class MLP:
                                     _dptr(order, torch.int32, "order"), int(steps), int(B),
                                     float(lr), float(w[0]), float(w[1]),
                                     _dptr(hist, torch.float32, "loss_hist"), _stream(stream)))
+        return hist
+
+    def grid_loss_grad(self, X, G, stream=None):
+        """mhdc_mlp_grid_loss_grad: G of shape (B, 40), the measured log time
+        ratios on the theta x n_b sweep grid (row-major, theta outer)."""
+        if tuple(G.shape) != (self._rows(X), GRID_POINTS):
+            raise ValueError("G must have shape (B, %d)" % GRID_POINTS)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        _check(lib().mhdc_mlp_grid_loss_grad(self._h, _dptr(X, torch.float32, "X"),
+                                             _dptr(G, torch.float32, "G"), X.shape[0],
+                                             _dptr(loss, torch.float32, "loss"),
+                                             _dptr(grad, torch.float32, "grad"),
+                                             _stream(stream)))
+        return loss, grad
+
+    def train_grid(self, X, G, order, steps, B, lr, stream=None):
+        """Adam with the grid loss over minibatches order[s*B:(s+1)*B]."""
+        if tuple(G.shape) != (self._rows(X), GRID_POINTS):
+            raise ValueError("G must have shape (N, %d)" % GRID_POINTS)
+        if order.numel() < int(steps) * int(B):
+            raise ValueError("order must hold steps * B row indices")
+        hist = torch.empty(int(steps), dtype=torch.float32, device=X.device)
+        _check(lib().mhdc_mlp_train_grid(self._h, _dptr(X, torch.float32, "X"),
+                                         _dptr(G, torch.float32, "G"), X.shape[0],
+                                         _dptr(order, torch.int32, "order"), int(steps),
+                                         int(B), float(lr),
+                                         _dptr(hist, torch.float32, "loss_hist"),
+                                         _stream(stream)))
         return hist
 
     def decide(self, X, stream=None):

@@ -100,6 +100,70 @@ def test_training_matches_oracle_adam_and_is_deterministic():
         assert np.array_equal(net3.params().view(np.int32), p0.view(np.int32))
 
 
+def _inside_params(X, seed):
+    """Parameters whose outputs on X fall inside the sweep grid's cells."""
+    p = _params(seed, noise=0.0).astype(np.float64) * 0.5
+    out, _ = S.forward(p, X)
+    p[-2] += 0.645 - out[:, 0].mean()
+    p[-1] += 8.45 - out[:, 1].mean()
+    return p.astype(np.float32)
+
+
+def test_grid_loss_gradient_matches_oracle():
+    """The grid loss of the measured-time landscape and its gradient by
+    backpropagation against the FP64 oracle, for outputs inside the grid and
+    outside it (where only the distance penalty acts on that output)."""
+    say("case: mlp grid loss / gradient")
+    rng = np.random.default_rng(8)
+    for B, shift in ((5, (0.0, 0.0)), (37, (0.0, 0.0)), (64, (0.6, -4.0)), (16, (-0.4, 6.0))):
+        X = rng.uniform(0, 1, size=(B, 66)).astype(np.float32)
+        p = _inside_params(X, 3 + B)
+        p[-2] += shift[0]
+        p[-1] += shift[1]
+        G = rng.uniform(0.0, 0.4, size=(B, 40)).astype(np.float32)
+        net = mhdc.MLP(p)
+        loss, g = net.grid_loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda())
+        L, gref = S.grid_loss_and_grad(p.astype(np.float64), X, G)
+        assert abs(loss.item() - L) <= 1e-5 * max(1.0, abs(L)), (loss.item(), L)
+        g = g.cpu().numpy()
+        assert np.allclose(g, gref, rtol=1e-3, atol=1e-5 * np.abs(gref).max())
+        net.close()
+
+
+def test_grid_training_matches_oracle_adam_and_is_deterministic():
+    say("case: mlp training with the grid loss")
+    rng = np.random.default_rng(9)
+    N, B, steps, lr = 200, 32, 5, 1e-3
+    X = rng.uniform(0, 1, size=(N, 66)).astype(np.float32)
+    G = rng.uniform(0.0, 0.4, size=(N, 40)).astype(np.float32)
+    order = np.concatenate([rng.permutation(N)[:B] for _ in range(steps)]).astype(np.int32)
+    p0 = _inside_params(X, 11)
+    Xd, Gd, od = (torch.from_numpy(a).cuda() for a in (X, G, order))
+    net = mhdc.MLP(p0)
+    hist = net.train_grid(Xd, Gd, od, steps, B, lr).cpu().numpy()
+    p_gpu = net.params()
+    p = p0.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(steps):
+        idx = order[t * B:(t + 1) * B]
+        L, g = S.grid_loss_and_grad(p, X[idx], G[idx])
+        assert abs(hist[t] - L) <= 1e-4 * max(1.0, L)
+        p, m, v = S.adam(p, g, m, v, t + 1, lr)
+    d = np.abs(p_gpu - p)
+    assert d.max() <= 2 * steps * lr
+    assert np.quantile(d, 0.99) <= 1e-5
+    net2 = mhdc.MLP(p0)
+    net2.train_grid(Xd, Gd, od, steps, B, lr)
+    assert np.array_equal(net2.params().view(np.int32), p_gpu.view(np.int32))
+    bad = od.clone()
+    bad[7] = N
+    net3 = mhdc.MLP(p0)
+    with pytest.raises(mhdc.MhdcError) as ei:
+        net3.train_grid(Xd, Gd, bad, steps, B, lr)
+    assert ei.value.name == "MHDC_ERR_INVALID_ARG"
+
+
 def test_training_reduces_loss():
     say("case: mlp training reduces loss")
     rng = np.random.default_rng(9)

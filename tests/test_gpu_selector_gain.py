@@ -32,7 +32,16 @@ def test_selector_gain_over_policy():
     say("refined (choice, grid neighbours, policy, n_b = 4096 timed): mean t/t_best %.4f, "
         "within 5%%: %.3f" % (rep["mean_ratio_refined"], rep["within_5pct_refined"]))
     assert rep["matrices"] == 240
-    # the refinement picks from a superset of the selection
+    # the learned result: the network's decisions alone (the judge keeps
+    # every one at the chosen tolerance), against the exhaustive search
+    say("network alone: within 5%% of the exhaustive best on %.3f, mean t/t_best %.4f; "
+        "judge override rate %.3f" % (rep["within_5pct_network_unjudged"],
+                                      rep["mean_ratio_network_unjudged"],
+                                      rep["judge_override_rate"]))
+    assert rep["within_5pct_network_unjudged"] >= 0.8
+    assert rep["mean_ratio_network_unjudged"] <= 1.03
+    # the refinement is a measured search around the decision (up to six
+    # more conversions and timings); it picks from a superset of the selection
     assert rep["mean_ratio_refined"] <= rep["mean_ratio_selected"]
     assert rep["within_5pct_refined"] >= rep["within_5pct_selected"]
     # and is within 5% of the exhaustive search on nearly every matrix
