@@ -103,6 +103,10 @@ int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
     int rc = check_operands_rm(m, X, ldx, Y, ldy, k);
     if (rc || m.n == 0)
         return rc;
+    // one right-hand side with unit strides is a plain vector: the
+    // single-column kernel, same bits
+    if (k == 1 && ldx == 1 && ldy == 1)
+        return launch_spmv(m, X, m.n, Y, m.n, 1, stream);
     const int32_t wg = m.launch.wg_size;
     const bool has_dia = m.K > 0;
     const bool has_rem = m.R > 0;

@@ -74,16 +74,18 @@ def test_rowmajor_padded_leading_dimensions():
     h = mhdc.MHDCMatrix.from_csr(*d, 128, 0.6)
     ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 128, 0.6)
     rng = np.random.default_rng(6)
-    k = 5
     Xw = rng.uniform(-1, 1, size=(m.n, 24))
-    Xd = _rm(Xw)[:, :k]
-    for mode in (1, 2):
-        h.set_launch(1, 256, 16, mode)
-        Yw = torch.full((m.n, 20), float("nan"), dtype=torch.float64, device="cuda")
-        h.spmm_rowmajor(Xd, Yw[:, :k])
-        _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
-                                for r in range(k)], "padded, csr_mode %d" % mode)
-        assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
+    # k = 5 in rows of 24 / 20; k = 1 with strides 24 / 20 (the row-slot
+    # kernel; unit strides take the single-column kernel)
+    for k in (5, 1):
+        Xd = _rm(Xw)[:, :k]
+        for mode in (1, 2):
+            h.set_launch(1, 256, 16, mode)
+            Yw = torch.full((m.n, 20), float("nan"), dtype=torch.float64, device="cuda")
+            h.spmm_rowmajor(Xd, Yw[:, :k])
+            _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
+                                    for r in range(k)], "padded k=%d, csr_mode %d" % (k, mode))
+            assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
     # argument checks: ld below k, overlapping X and Y
     buf = torch.zeros((m.n, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(mhdc.MhdcError) as e:
