@@ -244,8 +244,10 @@ int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
 /* Many M-HDC products in one launch.  Not in the paper; it addresses the
  * under-filled machine the paper reports when a matrix has too few row
  * blocks for the threads (Secs. 6.4.2-6.4.3, matrix #17).  All tiles of
- * all items form one sequence; a persistent grid of (CUs x resident
- * workgroups) takes tiles from an atomic counter until none is left.  Each
+ * all items form one sequence (items with more right-hand sides first, so
+ * the launch ends on its cheapest tiles); a persistent grid of (CUs x
+ * resident workgroups) takes tiles from an atomic counter until none is
+ * left.  Each
  * tile writes only its own rows, so item i's result is bit-identical to
  * mhdc_spmm(mats[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i]).
  *

@@ -28,6 +28,7 @@ struct BatchItem {
     int64_t tile_begin;  // first global tile number of this item
     int32_t kc;          // accumulator width class (1, 2, 4, 8, 16)
     int32_t rg;          // CSR part: stage values/columns (1) or products (0)
+    int32_t user;        // the item's index in the caller's arrays
 };
 
 // LDS bytes of the CSR-part variants batch_tile() can run at this width.
@@ -215,10 +216,23 @@ constexpr int64_t BATCH_MAX_TILES = (int64_t)INT32_MAX - (1LL << 20);
 int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int64_t *ldx,
                  double *const *Y, const int64_t *ldy)
 {
+    // Tiles are numbered item by item, the items with the most right-hand
+    // sides first (then the longest): the persistent grid then ends on the
+    // cheapest tiles, which shortens the tail where workgroups run out of
+    // work.  Each item still writes only its own Y.
+    std::vector<int32_t> order(b->count);
+    for (int32_t i = 0; i < b->count; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        if (b->nrhs[x] != b->nrhs[y])
+            return b->nrhs[x] > b->nrhs[y];
+        return b->mats[x]->n > b->mats[y]->n;
+    });
     std::vector<BatchItem> items(b->count, BatchItem{});
     int64_t tiles = 0;
     double flops = 0, bytes = 0;
-    for (int32_t i = 0; i < b->count; i++) {
+    for (int32_t slot = 0; slot < b->count; slot++) {
+        const int32_t i = order[slot];
         const BdcMatrix &m = *b->mats[i];
         const int32_t k = b->nrhs[i];
         const int64_t dflt = b->rowmajor ? k : m.n;
@@ -227,7 +241,8 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
                              : check_operands(m, X[i], lx, Y[i], ly, k);
         if (rc)
             return rc;
-        BatchItem &it = items[i];
+        BatchItem &it = items[slot];
+        it.user = i;
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
         it.kc = b->rowmajor ? rm_columns(k) : kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
         it.rg = (b->rowmajor ? rm_row_gather(m) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
@@ -424,11 +439,11 @@ int mhdc_batch_set_wg(mhdc_batch b, int32_t wg_size)
     std::vector<const double *> X(b->count);
     std::vector<double *> Y(b->count);
     std::vector<int64_t> lx(b->count), ly(b->count);
-    for (int32_t i = 0; i < b->count; i++) {
-        X[i] = b->host_items[i].a.X;
-        Y[i] = b->host_items[i].a.Y;
-        lx[i] = b->host_items[i].a.ldx;
-        ly[i] = b->host_items[i].a.ldy;
+    for (const BatchItem &it : b->host_items) {
+        X[it.user] = it.a.X;
+        Y[it.user] = it.a.Y;
+        lx[it.user] = it.a.ldx;
+        ly[it.user] = it.a.ldy;
     }
     int rc = upload_items(b, wg_size, X.data(), lx.data(), Y.data(), ly.data());
     if (!rc)
