@@ -460,17 +460,28 @@ def test_concurrent_streams_share_a_handle():
 
 
 def test_allocation_failure_leaks_nothing():
-    """Fail the k-th device allocation of a conversion for every k: each
-    attempt reports MHDC_ERR_OOM and returns all memory it took."""
+    """Fail the k-th device allocation of a conversion, a batch (both
+    layouts) and a selection for every k: each attempt reports MHDC_ERR_OOM
+    and returns all memory it took."""
     m = synth.partially_diagonal(12, 13)
     say("case: injected allocation failures")
     rp, ci, v = dev(m)
     L = mhdc.lib()
+    h0 = mhdc.MHDCMatrix.from_csr(rp, ci, v, 32, 0.6)
+    Xc = [torch.rand((3, m.n), dtype=torch.float64, device="cuda") for _ in range(2)]
+    Yc = [torch.empty_like(X) for X in Xc]
+    Xr = torch.rand((m.n, 3), dtype=torch.float64, device="cuda")
+    Yr = torch.empty_like(Xr)
+    from oracle import selector as S
+    net = mhdc.MLP(S.init_params(1))
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
     for make in (lambda: mhdc.MHDCMatrix.from_csr(rp, ci, v, 32, 0.6),
                  lambda: mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6),
-                 lambda: mhdc.CSRMatrix.from_csr(rp, ci, v)):
+                 lambda: mhdc.CSRMatrix.from_csr(rp, ci, v),
+                 lambda: mhdc.Batch([h0, h0], Xc, Ys=Yc),
+                 lambda: mhdc.Batch([h0], [Xr], Ys=[Yr], layout="rowmajor"),
+                 lambda: mhdc.select(rp, ci, v, model=net)[0]):
         k = 1
         while True:
             L.mhdc_debug_fail_alloc(k)
@@ -484,9 +495,11 @@ def test_allocation_failure_leaks_nothing():
                 L.mhdc_debug_fail_alloc(0)
             h.close()
             break
-        assert k > 2
+        assert k >= 2
     torch.cuda.synchronize()
     assert torch.cuda.mem_get_info()[0] >= free0 - (4 << 20)
+    net.close()
+    h0.close()
 
 
 @pytest.mark.parametrize("N,shift", [(100_003, 0), (100_000, 0), (1, 0), (2, 0), (4097, 1)])
