@@ -246,8 +246,10 @@ int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
  * blocks for the threads (Secs. 6.4.2-6.4.3, matrix #17).  All tiles of
  * all items form one sequence (items with more right-hand sides first, so
  * the launch ends on its cheapest tiles); a persistent grid of (CUs x
- * resident workgroups) takes tiles from an atomic counter until none is
- * left.  Each
+ * resident workgroups) takes tiles until none is left, each XCD from a
+ * counter of its own over runs of 16 consecutive tiles dealt to the XCDs in
+ * turn (neighbouring tiles share x through their near diagonals and then
+ * share an L2), taking other XCDs' tiles once its own have run out.  Each
  * tile writes only its own rows, so item i's result is bit-identical to
  * mhdc_spmm(mats[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i]).
  *
@@ -258,7 +260,7 @@ int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
  * wg_size: 64 or 256 lanes per workgroup (mhdc_batch_tune picks).
  * Y blocks must not overlap any X block.
  * One batch runs on one stream at a time: every launch of a batch (run or
- * graph_launch) takes tiles from the batch's single device counter, so two
+ * graph_launch) takes tiles from the batch's device counters, so two
  * launches of the same batch in flight together on different streams race
  * and give undefined results.  Launches ordered on one stream are safe;
  * for concurrent streams create one batch per stream (handles may be

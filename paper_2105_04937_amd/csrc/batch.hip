@@ -3,14 +3,14 @@
 // A batch holds up to thousands of (matrix, right-hand-side block) items of
 // uneven sizes.  The tiles of all items are numbered in one sequence; a
 // persistent grid sized to the machine (CUs x resident workgroups) takes
-// tiles from an atomic counter until the sequence is exhausted, so small
-// matrices never leave CUs idle the way one launch per matrix does.  Each
-// tile writes only its own rows (no floating-point atomics): the result of
-// every item is bit-identical to its single-matrix launch.
+// tiles from per-XCD atomic counters until the sequence is exhausted, so
+// small matrices never leave CUs idle the way one launch per matrix does.
+// Each tile writes only its own rows (no floating-point atomics): the result
+// of every item is bit-identical to its single-matrix launch.
 //
-// The counter is cleared by a one-thread kernel launched just before the
-// persistent kernel (no memset node, so the pair can be captured in a HIP
-// graph and replayed).  Descriptors live in device memory, so rebinding X/Y
+// The counters are cleared by a one-wavefront kernel launched just before
+// the persistent kernel (no memset node, so the pair can be captured in a
+// HIP graph and replayed).  Descriptors live in device memory, so rebinding X/Y
 // pointers takes effect in later replays without re-capture.
 #include "internal.h"
 #include "spmv_tile.h"
@@ -82,7 +82,48 @@ __device__ inline void batch_tile_rm(const BatchItem &it, int64_t local, double 
         spmv_tile_rm<WG, KC, true, true, false>(it.a, local, lds);
 }
 
-__global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
+// Tiles are dealt to the 8 XCDs in runs of BATCH_RUN consecutive tiles
+// (run r belongs to XCD r mod 8), and each XCD has a tile counter of its own
+// (BATCH_CTR_STRIDE ints apart).  Persistent workgroup w runs on XCD w mod 8
+// (a launch's workgroups are dispatched to the XCDs in turn) and takes its
+// XCD's tiles in order, so neighbouring tiles, which read the same x through
+// the near diagonals, are processed under one L2; a workgroup whose XCD has
+// run out takes the next XCD's tiles, until all eight have run out.
+constexpr int BATCH_XCDS = 8, BATCH_RUN = 16, BATCH_CTR_STRIDE = 32;
+
+__global__ void k_batch_reset(int32_t *counter)
+{
+    if (threadIdx.x < BATCH_XCDS)
+        counter[threadIdx.x * BATCH_CTR_STRIDE] = 0;
+}
+
+// The i-th tile of XCD x (strictly increasing in i).
+__device__ inline int64_t batch_xcd_tile(int x, int64_t i)
+{
+    const int64_t run = x + (int64_t)BATCH_XCDS * (i / BATCH_RUN);
+    return run * BATCH_RUN + i % BATCH_RUN;
+}
+
+// Next tile for this workgroup (uniform), or -1 when every XCD has run out.
+// *x is the XCD whose tiles the workgroup is taking; x0 its own.  Each
+// counter only grows, and a workgroup moves past an XCD at its first
+// exhausted answer, so every workgroup reaches -1.
+__device__ inline int64_t batch_take(int32_t *counter, int x0, int *x, int64_t total_tiles,
+                                     int64_t *s_tile)
+{
+    for (;;) {
+        if (threadIdx.x == 0)
+            *s_tile = batch_xcd_tile(*x, atomicAdd(&counter[*x * BATCH_CTR_STRIDE], 1));
+        __syncthreads();
+        const int64_t t = *s_tile;
+        __syncthreads();
+        if (t < total_tiles)
+            return t;
+        *x = (*x + 1) & (BATCH_XCDS - 1);
+        if (*x == x0)
+            return -1;
+    }
+}
 
 // Item owning global tile t: the last item with tile_begin <= t.
 __device__ inline int32_t batch_item_of(const BatchItem *__restrict__ items, int32_t count,
@@ -108,14 +149,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 {
     __shared__ double s_prod[batch_lds_doubles<WG>()];
     __shared__ int64_t s_tile;
+    const int x0 = blockIdx.x & (BATCH_XCDS - 1);
+    int x = x0;
     for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = atomicAdd(counter, 1);
-        __syncthreads();
-        const int64_t t = s_tile;
-        __syncthreads();
-        if (t >= total_tiles)
-            break;  // the counter only grows: every workgroup reaches this
+        const int64_t t = batch_take(counter, x0, &x, total_tiles, &s_tile);
+        if (t < 0)
+            break;
         const BatchItem &it = items[batch_item_of(items, count, t)];
         const int64_t local = t - it.tile_begin;
         switch (it.kc) {
@@ -140,14 +179,12 @@ __global__ __launch_bounds__(WG) void k_batch_rm(const BatchItem *__restrict__ i
     static_assert(TileShapeRm<WG, 2>::LDS_BYTES == TileShapeRm<WG, 16>::LDS_BYTES,
                   "one LDS size for every width");
     __shared__ int64_t s_tile;
+    const int x0 = blockIdx.x & (BATCH_XCDS - 1);
+    int x = x0;
     for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = atomicAdd(counter, 1);
-        __syncthreads();
-        const int64_t t = s_tile;
-        __syncthreads();
-        if (t >= total_tiles)
-            break;  // the counter only grows: every workgroup reaches this
+        const int64_t t = batch_take(counter, x0, &x, total_tiles, &s_tile);
+        if (t < 0)
+            break;
         const BatchItem &it = items[batch_item_of(items, count, t)];
         const int64_t local = t - it.tile_begin;
         switch (it.kc) {
@@ -205,9 +242,9 @@ int batch_grid(int wg, int rowmajor, int64_t total_tiles, int32_t *grid)
     return MHDC_OK;
 }
 
-// Largest tile count of a batch: the int32 tile counter runs past the last
-// tile by up to one increment per persistent workgroup (at most 256 CUs x 32
-// resident workgroups).
+// Largest tile count of a batch: a per-XCD int32 counter runs past its
+// XCD's last tile by up to one increment per persistent workgroup (at most
+// 256 CUs x 32 resident workgroups).
 constexpr int64_t BATCH_MAX_TILES = (int64_t)INT32_MAX - (1LL << 20);
 
 // Build the descriptor table for an X/Y binding and workgroup size, upload
@@ -272,7 +309,7 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
 {
     if (b->total_tiles == 0)
         return MHDC_OK;
-    k_batch_reset<<<1, 1, 0, s>>>(b->d_counter);
+    k_batch_reset<<<1, 64, 0, s>>>(b->d_counter);
     if (b->rowmajor && b->wg == 64)
         k_batch_rm<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
     else if (b->rowmajor)
@@ -357,7 +394,8 @@ mhdc_batch batch_create(int32_t count, const mhdc_handle *mats, const int32_t *n
     }
     int rc = dmalloc((void **)&b->d_items, sizeof(BatchItem) * (size_t)count, "batch items");
     if (!rc)
-        rc = dmalloc((void **)&b->d_counter, sizeof(int32_t), "batch counter");
+        rc = dmalloc((void **)&b->d_counter, sizeof(int32_t) * BATCH_XCDS * BATCH_CTR_STRIDE,
+                     "batch counters");
     if (!rc)
         rc = upload_items(b, wg_size, X, ldx, Y, ldy);
     if (rc) {
