@@ -168,12 +168,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 }
 
 // The persistent loop for a batch whose right-hand sides are stored row by
-// row.  A kernel of its own: its tile routine keeps KC rows per lane in
+// row.  Kernels of their own: the tile routine keeps KC/2 rows per lane in
 // registers and would not fit the column-major kernel's register cap.
 template <int WG>
-__global__ __launch_bounds__(WG) void k_batch_rm(const BatchItem *__restrict__ items,
-                                                 int32_t count, int64_t total_tiles,
-                                                 int32_t *counter)
+__device__ inline void batch_rm_loop(const BatchItem *__restrict__ items, int32_t count,
+                                     int64_t total_tiles, int32_t *counter)
 {
     __shared__ double s_prod[(TileShapeRm<WG, 2>::LDS_BYTES + 7) / 8];
     static_assert(TileShapeRm<WG, 2>::LDS_BYTES == TileShapeRm<WG, 16>::LDS_BYTES,
@@ -194,6 +193,22 @@ __global__ __launch_bounds__(WG) void k_batch_rm(const BatchItem *__restrict__ i
         default: batch_tile_rm<WG, 16>(it, local, s_prod); break;
         }
     }
+}
+
+// 64 lanes: one wave per SIMD (LDS-bound).
+__global__ __launch_bounds__(64) void k_batch_rm64(const BatchItem *__restrict__ items,
+                                                   int32_t count, int64_t total_tiles,
+                                                   int32_t *counter)
+{
+    batch_rm_loop<64>(items, count, total_tiles, counter);
+}
+
+// 256 lanes: held to three waves per SIMD (at most 168 VGPRs, no spills;
+// uncapped the compiler took 170 and only two fitted).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch_rm256(
+    const BatchItem *__restrict__ items, int32_t count, int64_t total_tiles, int32_t *counter)
+{
+    batch_rm_loop<256>(items, count, total_tiles, counter);
 }
 
 }  // namespace
@@ -222,8 +237,8 @@ namespace {
 const void *batch_kernel(int wg, int rowmajor)
 {
     if (rowmajor)
-        return wg == 64 ? reinterpret_cast<const void *>(k_batch_rm<64>)
-                        : reinterpret_cast<const void *>(k_batch_rm<256>);
+        return wg == 64 ? reinterpret_cast<const void *>(k_batch_rm64)
+                        : reinterpret_cast<const void *>(k_batch_rm256);
     return wg == 64 ? reinterpret_cast<const void *>(k_batch<64>)
                     : reinterpret_cast<const void *>(k_batch<256>);
 }
@@ -283,6 +298,7 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
         it.kc = b->rowmajor ? rm_columns(k) : kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
         it.rg = (b->rowmajor ? rm_row_gather(m) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
+        it.a.pairs = b->rowmajor && rm_pairs(X[i], lx, Y[i], ly) ? 1 : 0;
         it.tile_begin = tiles;
         tiles += ((int64_t)m.n + wg - 1) / wg;
         flops += 2.0 * (double)m.nnz * k;
@@ -311,10 +327,10 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
         return MHDC_OK;
     k_batch_reset<<<1, 64, 0, s>>>(b->d_counter);
     if (b->rowmajor && b->wg == 64)
-        k_batch_rm<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+        k_batch_rm64<<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
     else if (b->rowmajor)
-        k_batch_rm<256><<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles,
-                                                b->d_counter);
+        k_batch_rm256<<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles,
+                                              b->d_counter);
     else if (b->wg == 64)
         k_batch<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
     else

@@ -109,6 +109,9 @@ int check_launch(const mhdc_launch &cfg);
 // Row-major right-hand sides (element (i, r) at X[i*ldx + r], ldx >= k).
 int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
                       int64_t ldy, int32_t k);
+// Two adjacent columns per lane (16-byte loads and stores) in the row-major
+// kernel: X and Y 16-byte aligned, even leading dimensions.  Same bits.
+bool rm_pairs(const double *X, int64_t ldx, const double *Y, int64_t ldy);
 int rm_columns(int32_t k);  // accumulator width of the row-major kernel (2..16)
 // Row-major CSR part by row gathers (csr_mode 2, or csr_mode 0 and rows that
 // mostly repeat their neighbours' column offsets) rather than staged products.

@@ -91,6 +91,12 @@ bool rm_row_gather(const BdcMatrix &m)
     return m.launch.csr_mode == 2;
 }
 
+bool rm_pairs(const double *X, int64_t ldx, const double *Y, int64_t ldy)
+{
+    return ((uintptr_t)X & 15) == 0 && ((uintptr_t)Y & 15) == 0 && (ldx & 1) == 0 &&
+           (ldy & 1) == 0;
+}
+
 int rm_columns(int32_t k)
 {
     const int kc = kc_for(k);
@@ -120,6 +126,7 @@ int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, 1);
+        a.pairs = rm_pairs(X, ldx, Y, ldy);
         const int64_t tiles = ((int64_t)m.n + wg - 1) / wg;
         if (tiles > INT32_MAX)
             return set_error(MHDC_ERR_SIZE, "too many tiles");

@@ -62,6 +62,7 @@ struct SpmvArgs {
     int32_t uniform;
     int32_t remap;
     const uint32_t *rem_mask;  // one bit per 64 rows, or null: test rem_ptr
+    int32_t pairs;             // row-major kernel: 16-byte accesses of column pairs
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

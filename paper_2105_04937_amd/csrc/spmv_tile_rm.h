@@ -10,20 +10,25 @@
 // (Figs. 3, 8, 16).
 //
 // Work mapping (64-lane wavefronts): a wavefront owns 64 consecutive rows.
-// Its lanes are split into RPI = 64/KC row slots times KC columns: lane
-// (s, c) = (lane / KC, lane % KC) accumulates column c of the rows
-// wave_base + s + RPI*q, q < KC.  One load of X then covers RPI consecutive
-// rows times KC columns -- 64 consecutive doubles when ldx = KC -- for a
+// Each lane carries two adjacent columns, so a row takes LC = KC/2 lanes and
+// the wavefront splits into RPI = 64/LC row slots: lane (s, c) =
+// (lane / LC, lane % LC) accumulates columns 2c and 2c + 1 of the rows
+// wave_base + s + RPI*q, q < LC.  One load of X then covers RPI consecutive
+// rows times KC columns -- 128 consecutive doubles when ldx = KC -- for a
 // diagonal, and a remainder entry brings its column's row of X (KC
 // doubles, one cache line at KC = 16) instead of KC lines of KC separate
-// column vectors.
+// column vectors.  When X and Y are 16-byte aligned with even leading
+// dimensions (a.pairs) a lane moves its two columns with one 16-byte load
+// or store, otherwise with two 8-byte ones.  Against one column per lane
+// this halves the load instructions and cross-lane reads per diagonal and
+// doubles the bytes of each gather in flight.
 //   * DIA part: each lane loads the value of row wave_base + lane (one
 //     coalesced load per diagonal, non-temporal) and the lanes of row slot s
 //     read the value of their row q from lane s + RPI*q (cross-lane read).
 //   * CSR part: per chunk of the tile's entries, the wavefronts form the
-//     rounded products w * X[col*ldx + c] with lane (s, c) taking entries
-//     s, s + RPI, ... of its wavefront's share (independent gathers, RPI
-//     entries times KC columns per load, eight in flight per lane) and
+//     rounded products w * X[col*ldx + 2c + p] with lane (s, c) taking
+//     entries s, s + RPI, ... of its wavefront's share (independent gathers,
+//     RPI entries times KC columns per load, eight in flight per lane) and
 //     store them in LDS; each lane then adds the products of its rows'
 //     entries in column order, finding them through the tile's row
 //     pointers, which are staged in LDS once per tile.
@@ -36,7 +41,8 @@ namespace mhdc {
 template <int WG, int KC>
 struct TileShapeRm {
     static_assert(KC >= 2 && KC <= 16 && (KC & (KC - 1)) == 0, "2..16 columns");
-    static constexpr int RPI = 64 / KC;
+    static constexpr int LC = KC / 2;    // lanes per row (two columns each)
+    static constexpr int RPI = 64 / LC;  // rows per load instruction
     // remainder entries per chunk: 32 KB of products (staged products), or
     // 8 entries per lane of values and columns (row gathers); then the
     // tile's WG + 1 remainder row pointers
@@ -51,6 +57,24 @@ struct TileShapeRm {
     static constexpr int U = KC >= 8 ? 1 : 2;
 };
 
+typedef double rm_pair __attribute__((ext_vector_type(2)));
+
+// The lane's two columns of one row of X at p: v[0] when l0, v[1] when l1
+// (l1 implies l0), zero otherwise; one 16-byte load when pairs (p is then
+// 16-byte aligned).
+__device__ inline void rm_load(const double *__restrict__ p, bool l0, bool l1, bool pairs,
+                               double (&v)[2])
+{
+    if (pairs && l1) {
+        const rm_pair t = *reinterpret_cast<const rm_pair *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = l0 ? p[0] : 0.0;
+        v[1] = l1 ? p[1] : 0.0;
+    }
+}
+
 // RG: the CSR part's values and columns are staged and each lane gathers X
 // for its own rows' entries (rows of similar structure, such as stencils,
 // then read neighbouring rows of X in one load); otherwise the rounded
@@ -60,7 +84,9 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
 {
     // products are rounded before they are added: no multiply-add fusion
 #pragma clang fp contract(off)
+    constexpr int P = 2;  // columns per lane
     using Sh = TileShapeRm<WG, KC>;
+    constexpr int LC = Sh::LC;
     constexpr int RPI = Sh::RPI;
     constexpr int CH = Sh::CH;
     constexpr int U = Sh::U;
@@ -69,15 +95,20 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wave_base = tile_base + (int64_t)wave * 64;
-    const int s = lane / KC, c = lane % KC;
-    const bool col_live = c < a.k;
+    const int s = lane / LC, c0 = (lane % LC) * P;
+    // the lane's columns that exist
+    const bool l0 = c0 < a.k;
+    const bool l1 = c0 + 1 < a.k;
+    const bool pairs = a.pairs;
     const double *__restrict__ X = a.X;
     const int64_t ldx = a.ldx;
 
-    double acc[KC];
+    double acc[LC][P];
 #pragma unroll
-    for (int q = 0; q < KC; q++)
-        acc[q] = 0.0;
+    for (int q = 0; q < LC; q++)
+#pragma unroll
+        for (int p = 0; p < P; p++)
+            acc[q][p] = 0.0;
 
     static_assert(WG % 64 == 0 && 32 % (WG / 64) == 0, "tile must cover 64-row groups of one word");
     bool tile_rem = HAS_REM && a.has_rem;
@@ -112,9 +143,9 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                     }
                     __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < KC; q++) {
+                    for (int q = 0; q < LC; q++) {
                         const int64_t row = wave_base + s + RPI * q;
-                        if (row < n && col_live) {
+                        if (row < n && l0) {
                             const int r = (int)(row - tile_base);
                             const int32_t rs = s_rp[r], re = s_rp[r + 1];
                             const int32_t lo = rs > cb ? rs : cb;
@@ -122,14 +153,22 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                             int32_t e = lo;
                             for (; e + 2 <= hi; e += 2) {
                                 const double w0 = s_val[e - cb], w1 = s_val[e + 1 - cb];
-                                const double x0 = X[(int64_t)s_col[e - cb] * ldx + c];
-                                const double x1 = X[(int64_t)s_col[e + 1 - cb] * ldx + c];
-                                acc[q] = __dadd_rn(acc[q], __dmul_rn(w0, x0));
-                                acc[q] = __dadd_rn(acc[q], __dmul_rn(w1, x1));
+                                double x0[P], x1[P];
+                                rm_load(X + (int64_t)s_col[e - cb] * ldx + c0, l0, l1, pairs, x0);
+                                rm_load(X + (int64_t)s_col[e + 1 - cb] * ldx + c0, l0, l1, pairs, x1);
+#pragma unroll
+                                for (int p = 0; p < P; p++) {
+                                    acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w0, x0[p]));
+                                    acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w1, x1[p]));
+                                }
                             }
-                            if (e < hi)
-                                acc[q] = __dadd_rn(acc[q], __dmul_rn(s_val[e - cb],
-                                                                     X[(int64_t)s_col[e - cb] * ldx + c]));
+                            if (e < hi) {
+                                double x0[P];
+                                rm_load(X + (int64_t)s_col[e - cb] * ldx + c0, l0, l1, pairs, x0);
+#pragma unroll
+                                for (int p = 0; p < P; p++)
+                                    acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(s_val[e - cb], x0[p]));
+                            }
                         }
                     }
                     __syncthreads();
@@ -146,21 +185,26 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                         if (e < ce) {
                             const double w = __builtin_nontemporal_load(a.rem_val + e);
                             const int32_t col = __builtin_nontemporal_load(a.rem_col + e);
-                            const double xv = col_live ? X[(int64_t)col * ldx + c] : 0.0;
-                            s_prod[(e - cb) * KC + c] = __dmul_rn(w, xv);
+                            double xv[P];
+                            rm_load(X + (int64_t)col * ldx + c0, l0, l1, pairs, xv);
+#pragma unroll
+                            for (int p = 0; p < P; p++)
+                                s_prod[(e - cb) * KC + c0 + p] = __dmul_rn(w, xv[p]);
                         }
                     }
                     __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < KC; q++) {
+                    for (int q = 0; q < LC; q++) {
                         const int64_t row = wave_base + s + RPI * q;
-                        if (row < n && col_live) {
+                        if (row < n && l0) {
                             const int r = (int)(row - tile_base);
                             const int32_t rs = s_rp[r], re = s_rp[r + 1];
                             const int32_t lo = rs > cb ? rs : cb;
                             const int32_t hi = re < ce ? re : ce;
                             for (int32_t e = lo; e < hi; e++)
-                                acc[q] = __dadd_rn(acc[q], s_prod[(e - cb) * KC + c]);
+#pragma unroll
+                                for (int p = 0; p < P; p++)
+                                    acc[q][p] = __dadd_rn(acc[q][p], s_prod[(e - cb) * KC + c0 + p]);
                         }
                     }
                     __syncthreads();
@@ -189,33 +233,37 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                                                    a.dia_val + (int64_t)(kk + u) * a.n_b + t0 + lane)
                                          : 0.0;
                 }
-                double xv[U][KC];
-                bool in[U][KC];
+                double xv[U][LC][P];
+                bool in[U][LC];
 #pragma unroll
                 for (int u = 0; u < U; u++)
 #pragma unroll
-                    for (int q = 0; q < KC; q++) {
+                    for (int q = 0; q < LC; q++) {
                         const int64_t row = wave_base + s + RPI * q;
                         const int64_t j = row + off[u];
-                        in[u][q] = kk + u < kb1 && row < n && j >= 0 && j < n && col_live;
-                        xv[u][q] = in[u][q] ? X[j * ldx + c] : 0.0;
+                        in[u][q] = kk + u < kb1 && row < n && j >= 0 && j < n && l0;
+                        rm_load(X + (in[u][q] ? j : 0) * ldx + c0, in[u][q], in[u][q] && l1, pairs,
+                                   xv[u][q]);
                     }
 #pragma unroll
                 for (int u = 0; u < U; u++)
 #pragma unroll
-                    for (int q = 0; q < KC; q++) {
-                        const double w = __shfl(wl[u], s + RPI * q, 64);
+                    for (int q = 0; q < LC; q++) {
+                        // one lane per row: the lane's own value
+                        const double w = LC == 1 ? wl[u] : __shfl(wl[u], s + RPI * q, 64);
                         if (in[u][q])
-                            acc[q] = __dadd_rn(acc[q], __dmul_rn(w, xv[u][q]));
+#pragma unroll
+                            for (int p = 0; p < P; p++)
+                                acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w, xv[u][q][p]));
                     }
             }
         } else {
             // rows of one wavefront span several blocks: each row walks its
             // own block's list
 #pragma unroll
-            for (int q = 0; q < KC; q++) {
+            for (int q = 0; q < LC; q++) {
                 const int64_t row = wave_base + s + RPI * q;
-                if (row < n && col_live) {
+                if (row < n && l0) {
                     const int64_t ib = row / a.n_b;
                     const int64_t t = row - ib * a.n_b;
                     const int32_t kb0 = a.dia_ptr[ib], kb1 = a.dia_ptr[ib + 1];
@@ -223,7 +271,11 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                         const int64_t j = row + a.dia_off[kk];
                         if (j >= 0 && j < n) {
                             const double w = a.dia_val[(int64_t)kk * a.n_b + t];
-                            acc[q] = __dadd_rn(acc[q], __dmul_rn(w, X[j * ldx + c]));
+                            double xv[P];
+                            rm_load(X + j * ldx + c0, l0, l1, pairs, xv);
+#pragma unroll
+                            for (int p = 0; p < P; p++)
+                                acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w, xv[p]));
                         }
                     }
                 }
@@ -232,10 +284,21 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
     }
 
 #pragma unroll
-    for (int q = 0; q < KC; q++) {
+    for (int q = 0; q < LC; q++) {
         const int64_t row = wave_base + s + RPI * q;
-        if (row < n && col_live)
-            __builtin_nontemporal_store(acc[q], a.Y + row * a.ldy + c);
+        if (row < n && l0) {
+            double *y = a.Y + row * a.ldy + c0;
+            if (pairs && l1) {
+                rm_pair v;
+                v.x = acc[q][0];
+                v.y = acc[q][1];
+                __builtin_nontemporal_store(v, reinterpret_cast<rm_pair *>(y));
+            } else {
+                __builtin_nontemporal_store(acc[q][0], y);
+                if (l1)
+                    __builtin_nontemporal_store(acc[q][1], y + 1);
+            }
+        }
     }
 }
 

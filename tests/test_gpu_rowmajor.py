@@ -86,6 +86,22 @@ def test_rowmajor_padded_leading_dimensions():
             _check_cols(Yw[:, :k], [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r]))
                                     for r in range(k)], "padded k=%d, csr_mode %d" % (k, mode))
             assert torch.isnan(Yw[:, k:]).all(), "entries beyond k were written"
+    # X and Y only 8-byte aligned (a view one double into its storage), or an
+    # odd leading dimension with even k: each lane moves its two columns with
+    # two 8-byte accesses instead of one 16-byte one; same bits
+    h.set_launch(1, 256, 16, 0)
+    for k, ld, shift in ((16, 16, 1), (4, 6, 1), (4, 5, 0), (2, 3, 0)):
+        Xs = torch.empty(m.n * ld + shift, dtype=torch.float64, device="cuda")
+        Xv = Xs[shift:].view(m.n, ld)
+        Xv.copy_(_rm(Xw[:, :ld]))
+        Ys = torch.full((m.n * ld + shift,), float("nan"), dtype=torch.float64, device="cuda")
+        Yv = Ys[shift:].view(m.n, ld)
+        h.spmm_rowmajor(Xv[:, :k], Yv[:, :k])
+        want = [oracle.mhdc_spmv(ref, np.ascontiguousarray(Xw[:, r])) for r in range(k)]
+        _check_cols(Yv[:, :k], want, "k=%d ld=%d shift=%d" % (k, ld, shift))
+        assert torch.isnan(Yv[:, k:]).all(), "entries beyond k were written"
+        Ya = h.spmm_rowmajor(_rm(Xw[:, :k]))  # contiguous, 16-byte accesses at even k
+        assert_same_bits(Ya.cpu().numpy(), Yv[:, :k].cpu().numpy(), "k=%d aligned vs not" % k)
     # argument checks: ld below k, overlapping X and Y
     buf = torch.zeros((m.n, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(mhdc.MhdcError) as e:
