@@ -163,9 +163,11 @@ int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
  * (independent gathers; scattered columns), 2 = staged values and columns
  * with each lane gathering for its own rows (rows that repeat their
  * neighbours' offsets, such as stencils), 0 = 2 when row_repeat >= 0.5,
- * else 1.  rows_per_lane and rhs_group do not apply.  k = 1 with
- * ldx = ldy = 1 (a plain vector) runs the single-column kernel of
- * mhdc_spmv.  Asynchronous. */
+ * else 1.  rows_per_lane and rhs_group do not apply.  Each lane carries
+ * adjacent columns; X and Y 16-byte aligned with even ldx and ldy let it
+ * move them with 16-byte loads and stores (the fast case; otherwise 8-byte
+ * accesses, same bits).  k = 1 with ldx = ldy = 1 (a plain vector) runs
+ * the single-column kernel of mhdc_spmv.  Asynchronous. */
 int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y,
                        int64_t ldy, int32_t k, hipStream_t stream);
 

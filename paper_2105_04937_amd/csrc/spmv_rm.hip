@@ -9,9 +9,13 @@ namespace {
 
 using KernelFn = void (*)(SpmvArgs);
 
-// Row-major right-hand sides: one tile of WG rows per workgroup.
+// Row-major right-hand sides: one tile of WG rows per workgroup.  256-lane
+// tiles are held to four waves per SIMD, what their LDS allows (at 16
+// columns with both parts the compiler took 132 VGPRs and three fitted; the
+// cap costs a 20-byte spill and took the partially diagonal 192^3 case at
+// 16 columns from 2.47 to 2.13 ms).  64-lane tiles are LDS-bound at one.
 template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
-__global__ __launch_bounds__(WG) void k_spmm_rm(SpmvArgs a)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 4 : 1, 8))) void k_spmm_rm(SpmvArgs a)
 {
     __shared__ double s_lds[HAS_REM ? (TileShapeRm<WG, KC>::LDS_BYTES + 7) / 8 : 1];
     const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x, a.remap) : (int)blockIdx.x;

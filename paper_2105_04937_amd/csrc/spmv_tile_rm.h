@@ -10,7 +10,7 @@
 // (Figs. 3, 8, 16).
 //
 // Work mapping (64-lane wavefronts): a wavefront owns 64 consecutive rows.
-// Each lane carries two adjacent columns, so a row takes LC = KC/2 lanes and
+// Each lane carries P = 2 adjacent columns, so a row takes LC = KC/2 lanes and
 // the wavefront splits into RPI = 64/LC row slots: lane (s, c) =
 // (lane / LC, lane % LC) accumulates columns 2c and 2c + 1 of the rows
 // wave_base + s + RPI*q, q < LC.  One load of X then covers RPI consecutive
@@ -26,12 +26,16 @@
 //     coalesced load per diagonal, non-temporal) and the lanes of row slot s
 //     read the value of their row q from lane s + RPI*q (cross-lane read).
 //   * CSR part: per chunk of the tile's entries, the wavefronts form the
-//     rounded products w * X[col*ldx + 2c + p] with lane (s, c) taking
-//     entries s, s + RPI, ... of its wavefront's share (independent gathers,
-//     RPI entries times KC columns per load, eight in flight per lane) and
-//     store them in LDS; each lane then adds the products of its rows'
-//     entries in column order, finding them through the tile's row
-//     pointers, which are staged in LDS once per tile.
+//     rounded products w * X[col*ldx + c'] and store them in LDS, with four
+//     columns per lane from KC = 4 on (independent gathers of two 16-byte
+//     loads each, eight or more loads in flight per lane; each value and
+//     column index is then read by KC/4 lanes instead of KC/2; the DIA
+//     part keeps pairs, since with four columns per lane each 16-byte load
+//     instruction covers only half of every row's cache line); each lane
+//     then adds
+//     the products of its rows' entries in column order, finding them
+//     through the tile's row pointers, which are staged in LDS once per
+//     tile.
 #pragma once
 
 #include "spmv_tile.h"
@@ -41,7 +45,8 @@ namespace mhdc {
 template <int WG, int KC>
 struct TileShapeRm {
     static_assert(KC >= 2 && KC <= 16 && (KC & (KC - 1)) == 0, "2..16 columns");
-    static constexpr int LC = KC / 2;    // lanes per row (two columns each)
+    static constexpr int P = 2;          // columns per lane
+    static constexpr int LC = KC / P;    // lanes per row
     static constexpr int RPI = 64 / LC;  // rows per load instruction
     // remainder entries per chunk: 32 KB of products (staged products), or
     // 8 entries per lane of values and columns (row gathers); then the
@@ -50,28 +55,58 @@ struct TileShapeRm {
     static constexpr int CHR = WG * 8;
     static constexpr int STAGE_BYTES = CH * KC * 8 > CHR * 12 ? CH * KC * 8 : CHR * 12;
     static constexpr int LDS_BYTES = STAGE_BYTES + (WG + 1) * 4;
-    static_assert(CH % (WG / 64 * RPI) == 0, "chunk splits evenly over the slots");
+    // staged products are formed with GP columns per lane (a lane's two
+    // 16-byte loads per entry at 4 columns: half as many value and column
+    // loads per product as with pairs), entry slots of GRPI entries per load
+    static constexpr int GP = KC >= 4 ? 4 : 2;
+    static constexpr int GLC = KC / GP;
+    static constexpr int GRPI = 64 / GLC;
+    static_assert(CH % (WG / 64 * GRPI) == 0, "chunk splits evenly over the slots");
     // products per lane and chunk
-    static constexpr int PER_LANE = CH / (WG / 64) / RPI;
-    // diagonals in flight
-    static constexpr int U = KC >= 8 ? 1 : 2;
+    static constexpr int PER_LANE = CH / (WG / 64) / GRPI;
+    // diagonals in flight (two up to 8 columns: 2-5 % faster at 8 than one)
+    static constexpr int U = KC >= 16 ? 1 : 2;
 };
 
 typedef double rm_pair __attribute__((ext_vector_type(2)));
 
-// The lane's two columns of one row of X at p: v[0] when l0, v[1] when l1
-// (l1 implies l0), zero otherwise; one 16-byte load when pairs (p is then
-// 16-byte aligned).
-__device__ inline void rm_load(const double *__restrict__ p, bool l0, bool l1, bool pairs,
-                               double (&v)[2])
+// The lane's P columns of one row of X at p, of which the first nl exist
+// (the others read as zero): 16-byte loads of column pairs when pairs (p is
+// then 16-byte aligned), 8-byte loads otherwise.
+template <int P>
+__device__ inline void rm_load(const double *__restrict__ p, int nl, bool pairs, double (&v)[P])
 {
-    if (pairs && l1) {
-        const rm_pair t = *reinterpret_cast<const rm_pair *>(p);
-        v[0] = t.x;
-        v[1] = t.y;
-    } else {
-        v[0] = l0 ? p[0] : 0.0;
-        v[1] = l1 ? p[1] : 0.0;
+#pragma unroll
+    for (int h = 0; h < P; h += 2) {
+        if (pairs && nl >= h + 2) {
+            const rm_pair t = *reinterpret_cast<const rm_pair *>(p + h);
+            v[h] = t.x;
+            v[h + 1] = t.y;
+        } else {
+            v[h] = nl > h ? p[h] : 0.0;
+            v[h + 1] = nl > h + 1 ? p[h + 1] : 0.0;
+        }
+    }
+}
+
+// Stores the first nl of the lane's P columns to y (non-temporal), as
+// rm_load reads them.
+template <int P>
+__device__ inline void rm_store(double *p, int nl, bool pairs, const double (&v)[P])
+{
+#pragma unroll
+    for (int h = 0; h < P; h += 2) {
+        if (pairs && nl >= h + 2) {
+            rm_pair t;
+            t.x = v[h];
+            t.y = v[h + 1];
+            __builtin_nontemporal_store(t, reinterpret_cast<rm_pair *>(p + h));
+        } else {
+            if (nl > h)
+                __builtin_nontemporal_store(v[h], p + h);
+            if (nl > h + 1)
+                __builtin_nontemporal_store(v[h + 1], p + h + 1);
+        }
     }
 }
 
@@ -84,8 +119,8 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
 {
     // products are rounded before they are added: no multiply-add fusion
 #pragma clang fp contract(off)
-    constexpr int P = 2;  // columns per lane
     using Sh = TileShapeRm<WG, KC>;
+    constexpr int P = Sh::P;
     constexpr int LC = Sh::LC;
     constexpr int RPI = Sh::RPI;
     constexpr int CH = Sh::CH;
@@ -96,9 +131,9 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wave_base = tile_base + (int64_t)wave * 64;
     const int s = lane / LC, c0 = (lane % LC) * P;
-    // the lane's columns that exist
-    const bool l0 = c0 < a.k;
-    const bool l1 = c0 + 1 < a.k;
+    // the lane's columns that exist: nl of its P
+    const int nl = a.k - c0 < 0 ? 0 : a.k - c0 > P ? P : a.k - c0;
+    const bool l0 = nl > 0;
     const bool pairs = a.pairs;
     const double *__restrict__ X = a.X;
     const int64_t ldx = a.ldx;
@@ -154,8 +189,8 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                             for (; e + 2 <= hi; e += 2) {
                                 const double w0 = s_val[e - cb], w1 = s_val[e + 1 - cb];
                                 double x0[P], x1[P];
-                                rm_load(X + (int64_t)s_col[e - cb] * ldx + c0, l0, l1, pairs, x0);
-                                rm_load(X + (int64_t)s_col[e + 1 - cb] * ldx + c0, l0, l1, pairs, x1);
+                                rm_load<P>(X + (int64_t)s_col[e - cb] * ldx + c0, nl, pairs, x0);
+                                rm_load<P>(X + (int64_t)s_col[e + 1 - cb] * ldx + c0, nl, pairs, x1);
 #pragma unroll
                                 for (int p = 0; p < P; p++) {
                                     acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w0, x0[p]));
@@ -164,7 +199,7 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                             }
                             if (e < hi) {
                                 double x0[P];
-                                rm_load(X + (int64_t)s_col[e - cb] * ldx + c0, l0, l1, pairs, x0);
+                                rm_load<P>(X + (int64_t)s_col[e - cb] * ldx + c0, nl, pairs, x0);
 #pragma unroll
                                 for (int p = 0; p < P; p++)
                                     acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(s_val[e - cb], x0[p]));
@@ -179,17 +214,20 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                     // products: wavefront w takes chunk positions [w*CH/W, (w+1)*CH/W);
                     // eight gathers in flight per lane
                     const int32_t wb = cb + wave * (CH / (WG / 64));
+                    constexpr int GP = Sh::GP;
+                    const int gs = lane / Sh::GLC, gc0 = (lane % Sh::GLC) * GP;
+                    const int gnl = a.k - gc0 < 0 ? 0 : a.k - gc0 > GP ? GP : a.k - gc0;
 #pragma unroll 8
                     for (int j = 0; j < Sh::PER_LANE; j++) {
-                        const int32_t e = wb + s + RPI * j;
+                        const int32_t e = wb + gs + Sh::GRPI * j;
                         if (e < ce) {
                             const double w = __builtin_nontemporal_load(a.rem_val + e);
                             const int32_t col = __builtin_nontemporal_load(a.rem_col + e);
-                            double xv[P];
-                            rm_load(X + (int64_t)col * ldx + c0, l0, l1, pairs, xv);
+                            double xv[GP];
+                            rm_load<GP>(X + (int64_t)col * ldx + gc0, gnl, pairs, xv);
 #pragma unroll
-                            for (int p = 0; p < P; p++)
-                                s_prod[(e - cb) * KC + c0 + p] = __dmul_rn(w, xv[p]);
+                            for (int p = 0; p < GP; p++)
+                                s_prod[(e - cb) * KC + gc0 + p] = __dmul_rn(w, xv[p]);
                         }
                     }
                     __syncthreads();
@@ -242,7 +280,7 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                         const int64_t row = wave_base + s + RPI * q;
                         const int64_t j = row + off[u];
                         in[u][q] = kk + u < kb1 && row < n && j >= 0 && j < n && l0;
-                        rm_load(X + (in[u][q] ? j : 0) * ldx + c0, in[u][q], in[u][q] && l1, pairs,
+                        rm_load<P>(X + (in[u][q] ? j : 0) * ldx + c0, in[u][q] ? nl : 0, pairs,
                                    xv[u][q]);
                     }
 #pragma unroll
@@ -272,7 +310,7 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                         if (j >= 0 && j < n) {
                             const double w = a.dia_val[(int64_t)kk * a.n_b + t];
                             double xv[P];
-                            rm_load(X + j * ldx + c0, l0, l1, pairs, xv);
+                            rm_load<P>(X + j * ldx + c0, nl, pairs, xv);
 #pragma unroll
                             for (int p = 0; p < P; p++)
                                 acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w, xv[p]));
@@ -287,17 +325,7 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
     for (int q = 0; q < LC; q++) {
         const int64_t row = wave_base + s + RPI * q;
         if (row < n && l0) {
-            double *y = a.Y + row * a.ldy + c0;
-            if (pairs && l1) {
-                rm_pair v;
-                v.x = acc[q][0];
-                v.y = acc[q][1];
-                __builtin_nontemporal_store(v, reinterpret_cast<rm_pair *>(y));
-            } else {
-                __builtin_nontemporal_store(acc[q][0], y);
-                if (l1)
-                    __builtin_nontemporal_store(acc[q][1], y + 1);
-            }
+            rm_store<P>(a.Y + row * a.ldy + c0, nl, pairs, acc[q]);
         }
     }
 }
