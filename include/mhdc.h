@@ -107,18 +107,22 @@ typedef struct {
 /* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
  * k = 1): rows each lane owns (spaced one wavefront apart); wg_size in
  * {64, 256};
- * xcd_remap (0 or a power of two up to 64) places row tiles on the 8 XCDs:
- * 0 = dispatch order (tile w on XCD w mod 8), 1 = each XCD walks one
- * contiguous eighth of the tiles, C >= 2 = runs of C consecutive tiles per
- * XCD, the XCDs taking the runs in turn; csr_mode selects how the CSR part of a
- * tile is processed: 1 = each staging lane multiplies its entries by the
- * gathered x and stages the rounded products in LDS, 2 = values and columns
- * are staged and each lane gathers x for its own rows, 0 = 1 for one
- * right-hand side and 2 for several; rhs_group in {0, 1, 2, 4, 8, 16}:
+ * xcd_remap (0..64) places row tiles on the 8 XCDs: 0 = dispatch order
+ * (tile w on XCD w mod 8), 1 = each XCD walks one contiguous eighth of the
+ * tiles, C >= 2 = runs of C consecutive tiles per XCD, the XCDs taking the
+ * runs in turn (tile t + 8*C*j shares tile t's L2); csr_mode selects how
+ * the CSR part of a tile is processed: 1 = each staging lane multiplies its
+ * entries by the gathered x and stages the rounded products in LDS, 2 =
+ * values and columns are staged and each lane gathers x for its own rows,
+ * 0 = 1 for one right-hand side and 2 for several; rhs_group in {0, 1, 2,
+ * 4, 8, 16}:
  * right-hand sides processed per pass over a tile (0 = all, up to 16; a
  * further pass reads the tile's share of A again from the caches).  Every
- * variant gives the same bits.  A new handle starts with {1, 256, 16, c, 0}
- * for n >= 2^20 rows ({2, 256, 8, 0, 0} when it averages under 4 stored
+ * variant gives the same bits.  A new handle starts with {1, 256, C, c, 0}
+ * for n >= 2^20 rows, C in 8..16 chosen at conversion so that the x rows a
+ * tile reads through its farthest diagonal mostly lie in tiles on its own
+ * XCD (16 without a DIA part; 16 for the 7-point 256^3 stencil, 9 for the
+ * 27-point 192^3 one) ({2, 256, 8, 0, 0} when it averages under 4 stored
  * entries per row and n_b is a multiple of 128 or the whole matrix) and
  * {1, 64, 0, c, 0} below, where c = 2 for a handle without DIA part (CSR,
  * or K = 0) whose row_repeat (mhdc_info) is at least 0.5, else 0.  Set

@@ -16,12 +16,47 @@ thread_local std::string t_msg;
 std::atomic<int32_t> g_fail_countdown{0};
 }  // namespace
 
-mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat)
+int32_t xcd_run(int32_t far_offset, int32_t tile_rows)
 {
-    // Large matrices: 256-lane workgroups, runs of 4096 consecutive rows per
-    // XCD: a tile's neighbours, whose x entries it also reads through the
-    // near diagonals, then share its L2 (one contiguous eighth per XCD,
-    // xcd_remap = 1, is 5% slower).  One row per lane, or two where rows are
+    // A tile's rows [t*T, t*T + T) read x through the diagonal at +D in tiles
+    // t + D/T and t + D/T + 1 (rows weighted by how much of the window each
+    // holds); with runs of C tiles per XCD, tile u sits on XCD (u / C) mod 8.
+    // Score each C in [8, 16] by the share of those rows on the tile's own
+    // XCD over one round of 8*C tiles; ties go to the longer run (near
+    // neighbours in the same L2).  192^3 27-point stencil (D = N^2 + N + 1 =
+    // 37,057, T = 256): C = 9 (144 tiles = 16 runs), 442 against 460 us at
+    // C = 16 for one right-hand side; 256^3 7-point (D = 65,536): C = 16.
+    if (far_offset <= 0 || tile_rows <= 0)
+        return 16;
+    const int64_t d0 = far_offset / tile_rows, part = far_offset % tile_rows;
+    int32_t best = 16;
+    int64_t best_score = -1;
+    for (int32_t c = 16; c >= 8; c--) {
+        int64_t score = 0;  // rows on the own XCD, summed over one round
+        for (int64_t t = 0; t < 8 * c; t++) {
+            const int64_t x = (t / c) % 8;
+            if ((t + d0) / c % 8 == x)
+                score += tile_rows - part;
+            if (part && (t + d0 + 1) / c % 8 == x)
+                score += part;
+        }
+        // compare shares (score / (8c)) without division
+        if (best_score < 0 || score * 8 * best > best_score * 8 * c) {
+            best = c;
+            best_score = score;
+        }
+    }
+    return best;
+}
+
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat,
+                           int32_t far_offset)
+{
+    // Large matrices: 256-lane workgroups, runs of 8-16 consecutive tiles
+    // per XCD (xcd_run): a tile's neighbours, whose x entries it also reads
+    // through the near diagonals, then share its L2, and the run length puts
+    // the tiles its farthest diagonals reach there too (one contiguous eighth
+    // per XCD, xcd_remap = 1, is 5% slower).  One row per lane, or two where rows are
     // short (under 4 stored entries on average: a 256-row tile of the banded
     // 3-point matrix moves too little per workgroup and runs 33% slower than
     // a 512-row one); two rows per lane keep the wave-uniform diagonal path
@@ -42,7 +77,7 @@ mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repea
         const bool v2_uniform = n_b <= 0 || n_b >= n || n_b % 128 == 0;
         if (short_rows && v2_uniform)
             return mhdc_launch{2, 256, 8, 0, 0};
-        return mhdc_launch{1, 256, 16, mode1, 0};
+        return mhdc_launch{1, 256, xcd_run(far_offset, 256), mode1, 0};
     }
     return mhdc_launch{1, 64, 0, mode1, 0};
 }
@@ -99,7 +134,7 @@ H *make_handle(int kind, int32_t n, int32_t n_b, double theta)
     h->m.n = n;
     h->m.n_b = n_b;
     h->m.theta = theta;
-    h->m.launch = default_launch(n, n_b, 0, 0.0);
+    h->m.launch = default_launch(n, n_b, 0, 0.0, 0);
     (void)hipGetDevice(&h->m.device);
     return h;
 }
@@ -115,7 +150,8 @@ H *finish(H *h, int rc)
     // the staging choice by row repetition is made for handles without a
     // DIA part: next to partial diagonals the remainder is small, and with
     // it the staged products measured faster on the selector's matrices
-    h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz, h->m.K > 0 ? 0.0 : h->m.row_repeat);
+    h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz, h->m.K > 0 ? 0.0 : h->m.row_repeat,
+                                 h->m.far_offset);
     return h;
 }
 

@@ -9,6 +9,7 @@
 // faster one.
 #include "internal.h"
 
+#include <cstring>
 #include <vector>
 
 using namespace mhdc;
@@ -97,7 +98,16 @@ mhdc_handle mhdc_autotune(int32_t n, const int32_t *rowptr, const int32_t *colin
             break;
         }
         bool keep = false;
-        for (const mhdc_launch &shp : shapes) {
+        // the handle's own default first (its XCD runs fit the matrix's
+        // farthest diagonals), then the fixed shapes
+        mhdc_launch cands[1 + sizeof(shapes) / sizeof(shapes[0])];
+        int n_cand = 0;
+        cands[n_cand++] = h->m.launch;
+        for (const mhdc_launch &shp : shapes)
+            if (memcmp(&shp, &h->m.launch, sizeof(shp)) != 0)
+                cands[n_cand++] = shp;
+        for (int ci = 0; ci < n_cand && !rc; ci++) {
+            const mhdc_launch &shp = cands[ci];
             if ((shp.rows_per_lane == 4 && nrhs > 1) || (shp.rhs_group && shp.rhs_group >= nrhs))
                 continue;
             h->m.launch = shp;

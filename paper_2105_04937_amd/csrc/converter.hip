@@ -280,6 +280,25 @@ __global__ __launch_bounds__(CV_WG) void k_rem_mask(int32_t n, int64_t words,
     }
 }
 
+// Largest |offset| over the K selected diagonals (offsets lie in (-n, n), so
+// the absolute value fits int32): one atomic per wavefront.
+__global__ __launch_bounds__(CV_WG) void k_max_abs_offset(int64_t K, const int32_t *__restrict__ off,
+                                                          int32_t *out)
+{
+    int32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < K;
+         i += (int64_t)gridDim.x * CV_WG) {
+        const int32_t v = off[i] < 0 ? -off[i] : off[i];
+        m = v > m ? v : m;
+    }
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const int32_t o = __shfl_xor(m, sh, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m > 0)
+        atomicMax(out, m);
+}
+
 // One lane per row of a CSR-shaped pair (ptr, col): cnt[0] counts the rows
 // with entries, cnt[1] those of them whose column offsets col - row repeat
 // the previous row's (same length, same offsets in order).  Where most rows
@@ -469,6 +488,26 @@ int validate_csr(int32_t n, const int32_t *rowptr, const int32_t *colind, const 
     return MHDC_OK;
 }
 
+// Largest |offset| of the K diagonals in off (k_max_abs_offset).
+int max_abs_offset(int64_t K, const int32_t *off, int32_t *far)
+{
+    *far = 0;
+    if (K <= 0)
+        return MHDC_OK;
+    int32_t *d = nullptr;
+    int rc = dmalloc((void **)&d, sizeof(int32_t), "offset maximum");
+    if (rc)
+        return rc;
+    TempSet tmp;
+    tmp.add(d);
+    MHDC_HIP_CHECK(hipMemset(d, 0, sizeof(int32_t)));
+    k_max_abs_offset<<<grid_for(K, CV_WG, 1 << 10), CV_WG, 0, 0>>>(K, off, d);
+    if ((rc = launch_ok("offset maximum")))
+        return rc;
+    MHDC_HIP_CHECK(hipMemcpy(far, d, sizeof(int32_t), hipMemcpyDeviceToHost));
+    return MHDC_OK;
+}
+
 // Share of the CSR part's nonempty rows that repeat the previous row's
 // column offsets (k_row_repeat); 0 for an empty CSR part.
 int row_repeat_share(int32_t n, const int32_t *ptr, const int32_t *col, double *share)
@@ -652,6 +691,9 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
                 return rc;
         }
     }
+
+    if ((rc = max_abs_offset(K, m.dia_off, &m.far_offset)))
+        return rc;
 
     // DIA values: K * n_b slots, +0.0 padding.
     m.S = K * (int64_t)n_b;

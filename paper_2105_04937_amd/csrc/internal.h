@@ -37,6 +37,9 @@ struct BdcMatrix {
     // Share of the CSR part's nonempty rows whose column offsets repeat the
     // previous row's (0 when the CSR part is empty); picks the CSR mode.
     double row_repeat = 0.0;
+    // Largest |offset| of the DIA part's diagonals (0 without a DIA part):
+    // how far a tile's x rows lie from its own rows; picks the XCD run length.
+    int32_t far_offset = 0;
     int device = 0;
     mhdc_launch launch{2, 256, 0, 0, 0};
 };
@@ -125,7 +128,11 @@ int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
                        int64_t *total, hipStream_t stream);
 
 // api.hip: handle creation shared with the autotuner
-mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat);
+mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat,
+                           int32_t far_offset);
+// Run length (tiles per XCD run, 8..16) that keeps the x rows a tile reads
+// through its farthest diagonals in the tile's own XCD (16 without a DIA part).
+int32_t xcd_run(int32_t far_offset, int32_t tile_rows);
 
 }  // namespace mhdc
 

@@ -102,8 +102,8 @@ int check_launch(const mhdc_launch &cfg)
     if (cfg.csr_mode < 0 || cfg.csr_mode > 2)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "csr_mode must be 0, 1 or 2");
     const int r = cfg.xcd_remap;
-    if (r < 0 || r > 64 || (r & (r - 1)) != 0)
-        return set_error(MHDC_ERR_NOT_SUPPORTED, "xcd_remap must be 0 or a power of two up to 64");
+    if (r < 0 || r > 64)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "xcd_remap must lie in [0, 64]");
     const int g = cfg.rhs_group;
     if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16)
         return set_error(MHDC_ERR_NOT_SUPPORTED, "rhs_group must be 0, 1, 2, 4, 8 or 16");

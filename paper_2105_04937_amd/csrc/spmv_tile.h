@@ -67,11 +67,13 @@ struct SpmvArgs {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  remap = 1: XCD (w mod 8) walks one contiguous eighth of the G tiles.
-// remap = C >= 2 (a power of two): runs of C consecutive tiles go to one XCD
-// and the XCDs take the runs in turn, so a row tile's neighbours (whose x
-// entries it shares through near diagonals) mostly sit in the same L2 while
-// all XCDs still sweep the rows together.  Tiles past the last whole round
-// of 8*C keep dispatch order.  Both forms are bijections on [0, G).
+// remap = C >= 2: runs of C consecutive tiles go to one XCD and the XCDs
+// take the runs in turn, so a row tile's neighbours (whose x entries it
+// shares through near diagonals) mostly sit in the same L2 while all XCDs
+// still sweep the rows together; tile t + 8*C*j is on t's XCD, so a C that
+// divides the far diagonals' distance in tiles by 8 keeps those x rows in
+// the same L2 too.  Tiles past the last whole round of 8*C keep dispatch
+// order.  Both forms are bijections on [0, G).
 __device__ inline int xcd_tile(int w, int G, int remap)
 {
     const int x = w & 7, idx = w >> 3;
@@ -82,7 +84,8 @@ __device__ inline int xcd_tile(int w, int G, int remap)
     const int span = remap * 8;
     if (w >= (G / span) * span)
         return w;
-    return ((idx / remap) * 8 + x) * remap + (idx & (remap - 1));
+    const int run = idx / remap;
+    return (run * 8 + x) * remap + (idx - run * remap);
 }
 
 // Wave-uniform read of data no kernel writes while it runs (block and

@@ -91,6 +91,8 @@ def test_hepta256_spmv(hepta256, n_b):
     if n_b == 256:
         assert (inf["K"], inf["S"], inf["R"]) == (457_728, 117_178_368, 0)
         assert abs(inf["bytes_alg"] - 1_207_955_460) < 1
+        # farthest diagonal 65,536 rows = 256 tiles = 16 runs of 16: runs of 16
+        assert inf["xcd_remap"] == 16
     want = None
     if n_b in (256, 4096):
         ref = oracle.mhdc_from_csr(c.m.rowptr, c.m.colind, c.m.val, n_b, 0.6)
@@ -123,6 +125,7 @@ def test_partial192_mhdc(partial192, n_b, theta):
     c, m = partial192, partial192.m
     say("case: partially diagonal 192^3 n_b=%d theta=%.1f" % (n_b, theta))
     h = mhdc.MHDCMatrix.from_csr(*c.d, n_b, theta)
+    default_remap = h.info()["xcd_remap"]
     want = None
     if n_b in (64, 128):
         ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, theta)
@@ -134,6 +137,9 @@ def test_partial192_mhdc(partial192, n_b, theta):
     if (n_b, theta) == (128, 0.6):
         inf = h.info()
         assert 0.8 < inf["alpha"] < 0.95 and 0.2 < inf["beta"] < 0.3
+        # farthest diagonal N^2 + N + 1 = 37,057 rows, 144.75 tiles: runs of 9
+        # tiles put tile t + 144 on t's XCD (the default launch checked above)
+        assert default_remap == 9
 
 
 def test_partial192_hdc_csr(partial192):

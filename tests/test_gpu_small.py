@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 THETAS = [0.0, 0.5, 0.6, 2.0 / 3.0, 0.75, 1.0]
 SHAPES = [(1, 64, 0), (1, 64, 1), (2, 64, 1), (4, 64, 1), (1, 256, 1), (2, 256, 0),
           (2, 256, 1), (4, 256, 1), (1, 256, 0, 2), (2, 256, 0, 2), (1, 64, 0, 2, 0),
-          (2, 256, 0, 1, 0), (1, 64, 4), (2, 64, 2), (1, 64, 16), (1, 256, 8, 2, 0)]
+          (2, 256, 0, 1, 0), (1, 64, 4), (2, 64, 2), (1, 64, 16), (1, 256, 8, 2, 0),
+          (1, 64, 3), (1, 64, 9)]
 
 
 def _example_csr():
@@ -317,7 +318,7 @@ def test_error_paths():
     with pytest.raises(mhdc.MhdcError) as e:
         h.set_launch(3, 256, 1)
     assert e.value.name == "MHDC_ERR_NOT_SUPPORTED"
-    for remap in (3, 128, -1):
+    for remap in (65, 128, -1):
         with pytest.raises(mhdc.MhdcError) as e:
             h.set_launch(1, 256, remap)
         assert e.value.name == "MHDC_ERR_NOT_SUPPORTED"
