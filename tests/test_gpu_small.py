@@ -389,6 +389,43 @@ def test_row_repeat_picks_csr_mode():
         h.close()
 
 
+def _xcd_run_share(D, T, c):
+    """Share of the x rows a T-row tile reads through a diagonal D rows away
+    that lie in tiles on the tile's own XCD, with runs of c tiles per XCD
+    (tile u on XCD (u // c) % 8), over one round of 8c tiles: brute force."""
+    same = 0
+    for t in range(8 * c):
+        for row in range(t * T, t * T + T):
+            same += (row + D) // T // c % 8 == t // c % 8
+    return same / (8 * c * T)
+
+
+def test_default_xcd_runs_follow_the_farthest_diagonal():
+    """The default launch of a large handle takes the run length in [8, 16]
+    whose XCD keeps the most of the x rows its farthest kept diagonal reads
+    (ties to the longer run; 16 without a DIA part).  7-point 128^3: the
+    +-N^2 diagonals are 64 tiles away, one round of runs of 8.  The default
+    launch gives the oracle's bits."""
+    m = synth.heptadiagonal(128, 5)
+    say("case: XCD runs, 7-point 128^3 n=%d" % m.n)
+    shares = {c: _xcd_run_share(128 * 128, 256, c) for c in range(8, 17)}
+    want = max(range(16, 7, -1), key=lambda c: (shares[c], c))
+    assert want == 8 and shares[8] == 1.0 and shares[16] == 0.0
+    rp, ci, v = dev(m)
+    x = synth.vector(m.n, 9)
+    xd = torch.from_numpy(x).cuda()
+    h = mhdc.MHDCMatrix.from_csr(rp, ci, v, 256, 0.6)
+    assert h.info()["xcd_remap"] == want
+    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 256, 0.6)
+    assert_oracle_bits(h.spmv(xd), oracle.mhdc_spmv(ref, x), "M-HDC, runs of 8")
+    hd = mhdc.HDCMatrix.from_csr(rp, ci, v, 0.6)
+    assert hd.info()["xcd_remap"] == want
+    cs = mhdc.CSRMatrix.from_csr(rp, ci, v)
+    assert cs.info()["xcd_remap"] == 16  # no DIA part
+    for mat in (h, hd, cs):
+        mat.close()
+
+
 def test_conversion_and_spmv_are_deterministic():
     """Two conversions of the same matrix give the same arrays byte for byte,
     and two products the same bits, whatever order the census atomics took:
