@@ -9,12 +9,17 @@ everything the GPU side computes for it:
 
 * features: a census of partial diagonals at probe block size 256 (the same
   count N~(d, ib) as Sec. 4.3) summarised per offset bin;
-* a 66 -> 128 -> 128 -> 2 multilayer perceptron with ReLU hidden layers,
-  its squared-error loss, the gradient by backpropagation, and Adam;
+* a 66 -> 128 -> 128 -> 2 multilayer perceptron with ReLU hidden layers
+  (or 40 outputs, the scorer below), its squared-error loss, the gradient
+  by backpropagation, and Adam;
 * the grid loss: the network's output read as a point of the (theta,
   log2 n_b) grid on which the paper sweeps its parameters (Sec. 6.4.1),
   scored by the measured time there, interpolated bilinearly between the
-  grid points.
+  grid points;
+* the scorer: the same network with one output per point of that grid
+  (66 -> 128 -> 128 -> 40), each output an estimate of the point's log time
+  ratio, trained by a weighted squared error and read by taking the grid
+  point of the smallest estimate.
 
 Only tests import this module.
 """
@@ -27,7 +32,14 @@ N_IN = N_BINS + 2
 HIDDEN = 128
 N_OUT = 2
 PROBE_NB = 256
-SHAPES = [(HIDDEN, N_IN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (N_OUT, HIDDEN), (N_OUT,)]
+
+
+def shapes(n_out: int = N_OUT):
+    """Parameter blocks of the 66 -> 128 -> 128 -> n_out network."""
+    return [(HIDDEN, N_IN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (n_out, HIDDEN), (n_out,)]
+
+
+SHAPES = shapes(N_OUT)
 N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 25,346
 
 
@@ -88,12 +100,12 @@ def features(rowptr, colind, val, probe_nb: int = PROBE_NB) -> np.ndarray:
 
 
 # ----------------------------------------------------------------- network
-def init_params(seed: int) -> np.ndarray:
+def init_params(seed: int, n_out: int = N_OUT) -> np.ndarray:
     """He-uniform weights, zero biases, as one float32 vector in the order
-    W1 (128x66), b1, W2 (128x128), b2, W3 (2x128), b3 (row-major)."""
+    W1 (128x66), b1, W2 (128x128), b2, W3 (n_out x 128), b3 (row-major)."""
     rng = np.random.default_rng(seed)
     parts = []
-    for s in SHAPES:
+    for s in shapes(n_out):
         if len(s) == 2:
             lim = np.sqrt(6.0 / s[1])
             parts.append(rng.uniform(-lim, lim, size=s).ravel())
@@ -102,9 +114,16 @@ def init_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def n_outputs(p) -> int:
+    """Outputs of the network whose parameter vector is p (2 or 40)."""
+    rest = len(p) - (HIDDEN * N_IN + HIDDEN + HIDDEN * HIDDEN + HIDDEN)
+    assert rest % (HIDDEN + 1) == 0, "not a parameter vector of this network"
+    return rest // (HIDDEN + 1)
+
+
 def unpack(p):
     out, o = [], 0
-    for s in SHAPES:
+    for s in shapes(n_outputs(p)):
         k = int(np.prod(s))
         out.append(np.asarray(p[o:o + k], np.float64).reshape(s))
         o += k
@@ -217,3 +236,42 @@ def decode(out):
     theta = np.round(np.clip(out[:, 0], 0.5, 0.9) * 10.0) / 10.0
     nb = 2 ** np.clip(np.round(out[:, 1]), 5, 12).astype(np.int64)
     return theta, nb
+
+
+# ------------------------------------------------------------------ scorer
+N_SCORES = GRID_TH * GRID_NB          # one output per grid point, theta outer
+N_PARAMS_SCORER = sum(int(np.prod(s)) for s in shapes(N_SCORES))  # 30,248
+SCORE_TEMP, SCORE_FLOOR = 0.1, 0.05   # loss weight exp(-g / SCORE_TEMP) + SCORE_FLOOR
+
+
+def score_loss_and_grad(p, X, G):
+    """Scorer loss on grids G[B][40] (the log time ratios, theta outer):
+    L = sum_b sum_k w_bk (out_bk - G_bk)^2 / (40 B) with w = exp(-G / T) + F
+    (T = SCORE_TEMP, F = SCORE_FLOOR: the near-best points weigh most, the
+    rest enough to keep their order), and dL/dp by backpropagation."""
+    out, cache = forward(p, X)
+    B = cache[0].shape[0]
+    G = np.asarray(G, np.float64).reshape(B, N_SCORES)
+    w = np.exp(-G / SCORE_TEMP) + SCORE_FLOOR
+    diff = out - G
+    L = float(np.sum(w * diff * diff) / (N_SCORES * B))
+    return L, backward(p, cache, 2.0 * w * diff / (N_SCORES * B))
+
+
+def decode_scores(out):
+    """Scorer outputs [B][40] -> (theta, n_b, ok): the grid point k of the
+    smallest output (the first on ties), theta = 0.5 + 0.1 (k // 8), n_b =
+    2^(5 + k % 8); rows with a non-finite output give ok = 0 and the policy
+    point (0.6, 256)."""
+    out = np.atleast_2d(np.asarray(out, np.float64))
+    theta = np.full(out.shape[0], 0.6)
+    nb = np.full(out.shape[0], 256, np.int64)
+    ok = np.zeros(out.shape[0], np.int64)
+    for r, row in enumerate(out):
+        if not np.all(np.isfinite(row)):
+            continue
+        k = int(np.argmin(row))
+        theta[r] = round(0.5 + 0.1 * (k // GRID_NB), 1)
+        nb[r] = 2 ** (5 + k % GRID_NB)
+        ok[r] = 1
+    return theta, nb, ok

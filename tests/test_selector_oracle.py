@@ -163,3 +163,74 @@ def test_grid_backprop_matches_finite_differences():
         Lm, _ = S.grid_loss_and_grad(p - e, X, G)
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-5 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+# ---------------------------------------------------------------- scorer
+def test_scorer_param_count_and_layout():
+    """66 -> 128 -> 128 -> 40: 66*128 + 128 + 128*128 + 128 + 40*128 + 40
+    parameters; the output count is read back from a vector's length."""
+    assert S.N_PARAMS_SCORER == 66 * 128 + 128 + 128 * 128 + 128 + 40 * 128 + 40 == 30248
+    assert S.n_outputs(S.init_params(0, S.N_SCORES)) == 40
+    assert S.n_outputs(S.init_params(0)) == 2
+    assert S.forward(S.init_params(3, 40), np.ones((2, S.N_IN)))[0].shape == (2, 40)
+
+
+def _constant_scorer(c):
+    """Scorer parameters whose output is the constant vector c for every
+    input (all weights zero, b3 = c)."""
+    p = np.zeros(S.N_PARAMS_SCORER)
+    p[-S.N_SCORES:] = c
+    return p
+
+
+def test_scorer_loss_closed_forms():
+    """Zero at out = G; out = G + delta e_k costs w_k delta^2 / 40 with
+    w_k = exp(-G_k / T) + F: a near-best point (G_k = 0) weighs 1 + F, a
+    point twice as slow (G_k = log 2) exp(-log 2 / T) + F."""
+    rng = np.random.default_rng(5)
+    G = rng.uniform(0.0, 0.6, size=S.N_SCORES)
+    G[7] = 0.0
+    G[30] = np.log(2.0)
+    X = rng.uniform(0, 1, size=(1, S.N_IN))
+    L, g = S.score_loss_and_grad(_constant_scorer(G), X, G[None])
+    assert L == 0.0 and not np.any(g)
+    for k, wk in ((7, 1.0 + S.SCORE_FLOOR), (30, 2.0 ** (-1.0 / S.SCORE_TEMP) + S.SCORE_FLOOR)):
+        c = G.copy()
+        c[k] += 0.3
+        L, g = S.score_loss_and_grad(_constant_scorer(c), X, G[None])
+        assert abs(L - wk * 0.09 / 40) <= 1e-15
+        # only b3[k] and W3 row k (zero hidden activations) see the error
+        gb3 = g[-S.N_SCORES:]
+        assert abs(gb3[k] - 2 * wk * 0.3 / 40) <= 1e-15 and np.count_nonzero(gb3) == 1
+
+
+def test_scorer_backprop_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    p = S.init_params(2, S.N_SCORES).astype(np.float64) + rng.normal(0, 0.01, S.N_PARAMS_SCORER)
+    X = rng.uniform(0, 1, size=(5, S.N_IN))
+    G = rng.uniform(0.0, 0.5, size=(5, S.N_SCORES))
+    L, g = S.score_loss_and_grad(p, X, G)
+    idx = rng.choice(S.N_PARAMS_SCORER, size=300, replace=False)
+    idx = np.concatenate([idx, [S.N_PARAMS_SCORER - 1, S.N_PARAMS_SCORER - 41, 0]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(S.N_PARAMS_SCORER)
+        e[i] = h
+        fd = (S.score_loss_and_grad(p + e, X, G)[0] - S.score_loss_and_grad(p - e, X, G)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_decode_scores():
+    """Grid point k = 8 i + j (theta outer, the order of the training grids)
+    -> theta 0.5 + 0.1 i, n_b 2^(5 + j); the first of equal minima; a
+    non-finite row falls back to the policy point with ok = 0."""
+    out = np.ones((5, S.N_SCORES))
+    out[0, 0] = 0.0            # (0.5, 32)
+    out[1, 39] = -1.0          # (0.9, 4096)
+    out[2, 9] = out[2, 20] = -2.0   # tie: index 9 = (0.6, 64)
+    out[3, 12] = np.nan
+    out[4, 8 * 2 + 3] = 0.5    # (0.7, 256)
+    th, nb, ok = S.decode_scores(out)
+    assert list(th) == [0.5, 0.9, 0.6, 0.6, 0.7]
+    assert list(nb) == [32, 4096, 64, 256, 256]
+    assert list(ok) == [1, 1, 1, 0, 1]
