@@ -74,6 +74,8 @@ def main():
                          t_selected=round(t["selected"], 3), t_policy=round(t["policy"], 3),
                          t_best=round(t["best"], 3)))
         del rp, ci, v, x, y
+        if len(rows) % 40 == 0:
+            log("%d of %d matrices re-timed" % (len(rows), len(recs)))
     ts = np.array([q["t_selected"] for q in rows])
     tr = np.array([q["t_refined"] for q in rows])
     tp = np.array([q["t_policy"] for q in rows])

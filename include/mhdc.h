@@ -363,14 +363,28 @@ int mhdc_features(int32_t n, const int32_t *rowptr, const int32_t *colind,
 
 /* Network: 66 -> 128 -> 128 -> 2, ReLU hidden layers, FP32.  Parameters
  * (MHDC_MLP_PARAMS floats) in the order W1 (128x66), b1, W2 (128x128), b2,
- * W3 (2x128), b3, row-major.  Output o = (theta, log2 n_b). */
+ * W3 (2x128), b3, row-major.  Output o = (theta, log2 n_b).
+ * Scorer (not in the paper): the same network with 40 outputs, one per
+ * point of the sweep grid of Sec. 6.4.1 (theta = 0.5 + 0.1 i, i < 5, n_b =
+ * 2^(5+j), j < 8, output 8 i + j), each an estimate of that point's log
+ * time ratio log(t / t_best); MHDC_MLP_SCORER_PARAMS floats, W3 40x128 and
+ * b3 of 40.  The decision is the point of the smallest estimate.  Every
+ * entry point below takes either kind; out arrays hold B x
+ * mhdc_mlp_outputs(m) floats. */
 #define MHDC_MLP_PARAMS 25346
+#define MHDC_MLP_SCORER_PARAMS 30248
 typedef struct mhdc_mlp_s *mhdc_mlp;
 /* params_host: HOST array of initial parameters (the caller draws them). */
 mhdc_mlp mhdc_mlp_create(const float *params_host);
-/* Copy the current parameters to a HOST array (synchronous). */
+/* A scorer from MHDC_MLP_SCORER_PARAMS host floats. */
+mhdc_mlp mhdc_mlp_create_scorer(const float *params_host);
+/* Outputs per row: 2, or 40 for a scorer (0 and INVALID_ARG for NULL). */
+int32_t mhdc_mlp_outputs(mhdc_mlp m);
+/* Copy the current parameters to a HOST array (synchronous; 25346 or
+ * 30248 floats by kind). */
 int mhdc_mlp_get_params(mhdc_mlp m, float *params_host);
-/* out[B][2] = network(X[B][66]); device arrays; asynchronous on stream. */
+/* out[B][2] (scorer: [B][40]) = network(X[B][66]); device arrays;
+ * asynchronous on stream. */
 int mhdc_mlp_forward(mhdc_mlp m, const float *X, int32_t B, float *out,
                      hipStream_t stream);
 /* The forward pass of mhdc_mlp_forward for callers that cannot allocate
@@ -379,7 +393,7 @@ int mhdc_mlp_forward(mhdc_mlp m, const float *X, int32_t B, float *out,
  * out holds the same bits, but the two hidden layers live in a fixed 2 MB
  * device array of the library (one per GPU, kept until the process ends)
  * and nothing is allocated, freed or synchronised.  1 <= B <= 2048 (SIZE
- * beyond).  X[B][66] and out[B][2] are caller device arrays.  Calls on one
+ * beyond).  X[B][66] and out[B][outputs] are caller device arrays.  Calls on one
  * GPU share that array: two calls that overlap in time on the same GPU
  * (different streams, or different host threads) race and give undefined
  * results; order them on one stream.  Asynchronous on stream. */
@@ -387,7 +401,8 @@ int mhdc_mlp_forward_noalloc(mhdc_mlp m, const float *X, int32_t B, float *out,
                              hipStream_t stream);
 /* loss = sum_r (w0 (o_r0 - T_r0)^2 + w1 (o_r1 - T_r1)^2) / B and its
  * gradient (MHDC_MLP_PARAMS floats, parameter order) by backpropagation;
- * device arrays; asynchronous on stream. */
+ * device arrays; asynchronous on stream.  2-output networks only
+ * (NOT_SUPPORTED for a scorer; so is mhdc_mlp_train). */
 int mhdc_mlp_loss_grad(mhdc_mlp m, const float *X, const float *T, int32_t B,
                        float w0, float w1, float *loss, float *grad,
                        hipStream_t stream);
@@ -409,7 +424,10 @@ int mhdc_mlp_train(mhdc_mlp m, const float *X, const float *T, int32_t N,
  * (the cell above a point on an inner grid line), and outside the grid's
  * box by the value at the clamped point plus |theta - clamp| + |log2 n_b -
  * clamp|; loss = sum_r score_r / B and its gradient (MHDC_MLP_PARAMS
- * floats).  Device arrays; asynchronous on stream. */
+ * floats).  For a scorer, whose outputs o_r[k] estimate G[r][k], the loss
+ * is instead sum_r sum_k w_rk (o_r[k] - G[r][k])^2 / (40 B) with w =
+ * exp(-G / 0.1) + 0.05 (the near-best points weigh most), gradient
+ * MHDC_MLP_SCORER_PARAMS floats.  Device arrays; asynchronous on stream. */
 int mhdc_mlp_grid_loss_grad(mhdc_mlp m, const float *X, const float *G, int32_t B,
                             float *loss, float *grad, hipStream_t stream);
 /* As mhdc_mlp_train with the grid loss: G[N][40] as above replaces the
@@ -420,8 +438,10 @@ int mhdc_mlp_train_grid(mhdc_mlp m, const float *X, const float *G, int32_t N,
                         float *loss_hist, hipStream_t stream);
 /* Decisions for B feature rows: theta[r] = round(10 clip(o_r0, 0.5, 0.9))/10
  * (the theta grid of Sec. 6.4.1), n_b[r] = 2^clip(round(o_r1), 5, 12),
- * ok[r] = 0 (and the policy 0.6 / 256) for a non-finite output.  Device
- * arrays; asynchronous on stream. */
+ * ok[r] = 0 (and the policy 0.6 / 256) for a non-finite output.  A scorer
+ * takes the grid point k of its smallest output (the first of equal ones):
+ * theta 0.5 + 0.1 (k / 8), n_b 2^(5 + k % 8); ok = 0 and the policy if any
+ * output is not finite.  Device arrays; asynchronous on stream. */
 int mhdc_mlp_decide(mhdc_mlp m, const float *X, int32_t B, double *theta,
                     int32_t *n_b, int32_t *ok, hipStream_t stream);
 void mhdc_mlp_destroy(mhdc_mlp m);

@@ -16,6 +16,9 @@
 //
 // Network: 66 -> 128 -> 128 -> 2, ReLU hidden layers, FP32 parameters in
 // one vector (W1 128x66, b1, W2 128x128, b2, W3 2x128, b3, row-major).
+// Scorer: the same network with 40 outputs (W3 40x128, b3), one per point
+// of the (theta, n_b) sweep grid, each an estimate of that point's log
+// time ratio; the decision is the point of the smallest estimate.
 // Every reduction (over inputs in the forward pass, over the minibatch in
 // the weight gradients) runs in a fixed order in one thread, so training is
 // deterministic.  One training step (minibatch gather, forward, loss,
@@ -46,6 +49,12 @@ constexpr int P_W3 = P_B2 + HID;
 constexpr int P_B3 = P_W3 + N_OUT * HID;
 constexpr int N_PARAMS = P_B3 + N_OUT;
 static_assert(N_PARAMS == 25346, "parameter layout");
+// offsets of b3 and parameter counts for n_out outputs
+constexpr int p_b3(int n_out) { return P_W3 + n_out * HID; }
+constexpr int n_params(int n_out) { return p_b3(n_out) + n_out; }
+static_assert(n_params(N_GRID) == 30248, "scorer parameter layout");
+// scorer loss weight exp(-g / SCORE_TEMP) + SCORE_FLOOR per grid point
+constexpr float SCORE_TEMP = 0.1f, SCORE_FLOOR = 0.05f;
 constexpr int TW = 256;
 
 inline unsigned blocks_for(int64_t items) { return (unsigned)((items + TW - 1) / TW); }
@@ -306,6 +315,62 @@ __global__ __launch_bounds__(TW) void k_grid_loss_grad(const float *__restrict__
     }
 }
 
+// Scorer loss: out and G are [B][N_GRID] (estimates and measured log time
+// ratios, theta outer); loss = sum w (out - G)^2 / (N_GRID B) with w =
+// exp(-G / SCORE_TEMP) + SCORE_FLOOR (fixed-order tree), d_out = 2 w (out -
+// G) / (N_GRID B).  One workgroup.
+__global__ __launch_bounds__(TW) void k_score_loss_grad(const float *__restrict__ out,
+                                                        const float *__restrict__ G, int B,
+                                                        float *__restrict__ d_out,
+                                                        float *loss_at, const int32_t *local_step)
+{
+    __shared__ float part[TW];
+    const float norm = (float)(N_GRID * B);
+    float acc = 0.0f;
+    for (int idx = threadIdx.x; idx < B * N_GRID; idx += TW) {
+        const float g = G[idx];
+        const float w = expf(-g / SCORE_TEMP) + SCORE_FLOOR;
+        const float d = out[idx] - g;
+        d_out[idx] = 2.0f * w * d / norm;
+        acc += w * d * d;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = TW / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float *dst = loss_at + (local_step ? *local_step : 0);
+        *dst = part[0] / norm;
+    }
+}
+
+// (theta, n_b) from each scorer output row: the grid point k of the
+// smallest estimate (the first of equal ones), theta = 0.5 + 0.1 (k / 8),
+// n_b = 2^(5 + k % 8); ok = 0 for a row with a non-finite estimate (then
+// theta = 0.6, n_b = 256).
+__global__ void k_decode_scores(const float *__restrict__ out, int B, double *theta, int32_t *nb,
+                                int32_t *ok)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B)
+        return;
+    const float *o = out + (int64_t)r * N_GRID;
+    bool fin = true;
+    int k = 0;
+    for (int i = 0; i < N_GRID; i++) {
+        fin = fin && isfinite(o[i]);
+        if (o[i] < o[k])
+            k = i;
+    }
+    ok[r] = fin ? 1 : 0;
+    const int i = fin ? k / GRID_NB : 1, j = fin ? k % GRID_NB : 3;
+    theta[r] = (double)(5 + i) / 10.0;
+    nb[r] = 1 << (5 + j);
+}
+
 // (theta, n_b) from each network output row: theta = round(10 clip(o0, .5,
 // .9))/10 (the paper's theta grid, Sec. 6.4.1), n_b = 2^clip(round(o1), 5,
 // 12); ok = 0 for non-finite outputs (then theta = 0.6, n_b = 256).
@@ -381,6 +446,8 @@ int noalloc_scratch(float **out)
 using namespace mhdc;
 
 struct mhdc_mlp_s {
+    int32_t n_out = N_OUT;  // 2 (theta, log2 n_b) or N_GRID (scorer)
+    int32_t n_par = N_PARAMS;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     int32_t *step = nullptr, *local_step = nullptr;
     int32_t cap = 0;  // minibatch capacity of the buffers below
@@ -409,8 +476,8 @@ int ensure_buffers(mhdc_mlp_s *M, int32_t B)
         (rc = dmalloc((void **)&M->Tb, f * B * N_GRID, "mlp Tb")) ||
         (rc = dmalloc((void **)&M->h1, f * B * HID, "mlp h1")) ||
         (rc = dmalloc((void **)&M->h2, f * B * HID, "mlp h2")) ||
-        (rc = dmalloc((void **)&M->out, f * B * N_OUT, "mlp out")) ||
-        (rc = dmalloc((void **)&M->d_out, f * B * N_OUT, "mlp d_out")) ||
+        (rc = dmalloc((void **)&M->out, f * B * M->n_out, "mlp out")) ||
+        (rc = dmalloc((void **)&M->d_out, f * B * M->n_out, "mlp d_out")) ||
         (rc = dmalloc((void **)&M->d_h2, f * B * HID, "mlp d_h2")) ||
         (rc = dmalloc((void **)&M->d_h1, f * B * HID, "mlp d_h1"))) {
         free_buffers(M);
@@ -424,13 +491,14 @@ void enqueue_forward(mhdc_mlp_s *M, const float *X, int B, hipStream_t s)
 {
     k_dense_fwd<<<blocks_for(B * HID), TW, 0, s>>>(X, N_IN, M->p + P_W1, M->p + P_B1, HID, M->h1, B, 1);
     k_dense_fwd<<<blocks_for(B * HID), TW, 0, s>>>(M->h1, HID, M->p + P_W2, M->p + P_B2, HID, M->h2, B, 1);
-    k_dense_fwd<<<blocks_for(B * N_OUT), TW, 0, s>>>(M->h2, HID, M->p + P_W3, M->p + P_B3, N_OUT, M->out, B, 0);
+    k_dense_fwd<<<blocks_for(B * M->n_out), TW, 0, s>>>(M->h2, HID, M->p + P_W3, M->p + p_b3(M->n_out), M->n_out, M->out, B, 0);
 }
 
 void enqueue_backward(mhdc_mlp_s *M, const float *X, int B, hipStream_t s)
 {
-    k_dense_bwd_w<<<blocks_for(N_OUT * (HID + 1)), TW, 0, s>>>(M->d_out, M->h2, B, HID, N_OUT, M->g + P_W3, M->g + P_B3);
-    k_dense_bwd_x<<<blocks_for(B * HID), TW, 0, s>>>(M->d_out, M->p + P_W3, M->h2, B, HID, N_OUT, M->d_h2);
+    const int no = M->n_out;
+    k_dense_bwd_w<<<blocks_for(no * (HID + 1)), TW, 0, s>>>(M->d_out, M->h2, B, HID, no, M->g + P_W3, M->g + p_b3(no));
+    k_dense_bwd_x<<<blocks_for(B * HID), TW, 0, s>>>(M->d_out, M->p + P_W3, M->h2, B, HID, no, M->d_h2);
     k_dense_bwd_w<<<blocks_for(HID * (HID + 1)), TW, 0, s>>>(M->d_h2, M->h1, B, HID, HID, M->g + P_W2, M->g + P_B2);
     k_dense_bwd_x<<<blocks_for(B * HID), TW, 0, s>>>(M->d_h2, M->p + P_W2, M->h1, B, HID, HID, M->d_h1);
     k_dense_bwd_w<<<blocks_for(HID * (N_IN + 1)), TW, 0, s>>>(M->d_h1, X, B, N_IN, HID, M->g + P_W1, M->g + P_B1);
@@ -501,7 +569,11 @@ int mhdc_features(int32_t n, const int32_t *rowptr, const int32_t *colind, const
     return rc;
 }
 
-mhdc_mlp mhdc_mlp_create(const float *params_host)
+}  // extern "C"
+
+namespace {
+
+mhdc_mlp create_impl(const float *params_host, int32_t n_out)
 {
     clear_error();
     if (!params_host) {
@@ -513,7 +585,9 @@ mhdc_mlp mhdc_mlp_create(const float *params_host)
         set_error(MHDC_ERR_OOM, "host allocation of the network failed");
         return nullptr;
     }
-    const size_t pb = sizeof(float) * N_PARAMS;
+    M->n_out = n_out;
+    M->n_par = n_params(n_out);
+    const size_t pb = sizeof(float) * M->n_par;
     int rc;
     if ((rc = dmalloc((void **)&M->p, pb, "mlp params")) ||
         (rc = dmalloc((void **)&M->g, pb, "mlp grads")) ||
@@ -535,13 +609,34 @@ mhdc_mlp mhdc_mlp_create(const float *params_host)
     return M;
 }
 
+}  // namespace
+
+extern "C" {
+
+mhdc_mlp mhdc_mlp_create(const float *params_host) { return create_impl(params_host, N_OUT); }
+
+mhdc_mlp mhdc_mlp_create_scorer(const float *params_host)
+{
+    return create_impl(params_host, N_GRID);
+}
+
+int32_t mhdc_mlp_outputs(mhdc_mlp M)
+{
+    clear_error();
+    if (!M) {
+        set_error(MHDC_ERR_INVALID_ARG, "network is NULL");
+        return 0;
+    }
+    return M->n_out;
+}
+
 int mhdc_mlp_get_params(mhdc_mlp M, float *params_host)
 {
     clear_error();
     if (!M || !params_host)
         return set_error(MHDC_ERR_INVALID_ARG, "network or buffer is NULL");
     MHDC_HIP_CHECK(hipDeviceSynchronize());
-    MHDC_HIP_CHECK(hipMemcpy(params_host, M->p, sizeof(float) * N_PARAMS, hipMemcpyDeviceToHost));
+    MHDC_HIP_CHECK(hipMemcpy(params_host, M->p, sizeof(float) * M->n_par, hipMemcpyDeviceToHost));
     return MHDC_OK;
 }
 
@@ -555,7 +650,7 @@ int mhdc_mlp_forward(mhdc_mlp M, const float *X, int32_t B, float *out, hipStrea
     if (rc)
         return rc;
     enqueue_forward(M, X, B, stream);
-    MHDC_HIP_CHECK(hipMemcpyAsync(out, M->out, sizeof(float) * B * N_OUT,
+    MHDC_HIP_CHECK(hipMemcpyAsync(out, M->out, sizeof(float) * B * M->n_out,
                                   hipMemcpyDeviceToDevice, stream));
     return launch_ok("mlp forward");
 }
@@ -578,7 +673,7 @@ int mhdc_mlp_forward_noalloc(mhdc_mlp M, const float *X, int32_t B, float *out,
     // outputs are the same bits; the last layer writes `out` directly
     k_dense_fwd<<<blocks_for(B * HID), TW, 0, stream>>>(X, N_IN, M->p + P_W1, M->p + P_B1, HID, h1, B, 1);
     k_dense_fwd<<<blocks_for(B * HID), TW, 0, stream>>>(h1, HID, M->p + P_W2, M->p + P_B2, HID, h2, B, 1);
-    k_dense_fwd<<<blocks_for(B * N_OUT), TW, 0, stream>>>(h2, HID, M->p + P_W3, M->p + P_B3, N_OUT, out, B, 0);
+    k_dense_fwd<<<blocks_for(B * M->n_out), TW, 0, stream>>>(h2, HID, M->p + P_W3, M->p + p_b3(M->n_out), M->n_out, out, B, 0);
     return launch_ok("mlp forward (no allocation)");
 }
 
@@ -588,6 +683,8 @@ int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, fl
     clear_error();
     if (!M || !X || !T || !loss || !grad || B < 1)
         return set_error(MHDC_ERR_INVALID_ARG, "network, X, T, loss, grad and B >= 1 required");
+    if (M->n_out != N_OUT)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "the squared error to targets is for 2-output networks");
     MHDC_HIP_CHECK(hipStreamSynchronize(stream));
     int rc = ensure_buffers(M, B);
     if (rc)
@@ -595,7 +692,7 @@ int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, fl
     enqueue_forward(M, X, B, stream);
     k_loss_grad<<<1, TW, 0, stream>>>(M->out, T, B, w0, w1, M->d_out, loss, nullptr);
     enqueue_backward(M, X, B, stream);
-    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice,
+    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * M->n_par, hipMemcpyDeviceToDevice,
                                   stream));
     return launch_ok("mlp loss/grad");
 }
@@ -604,9 +701,10 @@ int mhdc_mlp_loss_grad(mhdc_mlp M, const float *X, const float *T, int32_t B, fl
 
 namespace {
 
-// Training shared by the two losses: grid = false, T holds N_OUT target
+// Training shared by the losses: grid = false, T holds N_OUT target
 // outputs per row and the loss is the weighted squared error; grid = true,
-// T holds the N_GRID grid values per row and the loss is the grid loss.
+// T holds the N_GRID grid values per row and the loss is the grid loss (a
+// 2-output network) or the scorer loss (a scorer).
 int train_impl(mhdc_mlp M, const float *X, const float *T, int32_t N, const int32_t *order,
                int64_t steps, int32_t B, float lr, float w0, float w1, float *loss_hist,
                hipStream_t stream, bool grid)
@@ -615,6 +713,8 @@ int train_impl(mhdc_mlp M, const float *X, const float *T, int32_t N, const int3
         return set_error(MHDC_ERR_INVALID_ARG, "bad training arguments");
     if (steps * (int64_t)B > INT32_MAX)
         return set_error(MHDC_ERR_SIZE, "steps * B exceeds the order index range");
+    if (!grid && M->n_out != N_OUT)
+        return set_error(MHDC_ERR_NOT_SUPPORTED, "the squared error to targets is for 2-output networks");
     MHDC_HIP_CHECK(hipStreamSynchronize(stream));
     int rc = ensure_buffers(M, B);
     if (rc)
@@ -653,14 +753,17 @@ int train_impl(mhdc_mlp M, const float *X, const float *T, int32_t N, const int3
         k_gather<<<blocks_for(B * (N_IN + tdim)), TW, 0, cs>>>(X, T, tdim, order, M->local_step, B,
                                                               M->Xb, M->Tb);
         enqueue_forward(M, M->Xb, B, cs);
-        if (grid)
+        if (grid && M->n_out == N_GRID)
+            k_score_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, M->d_out, loss_hist,
+                                                M->local_step);
+        else if (grid)
             k_grid_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, M->d_out, loss_hist,
                                                M->local_step);
         else
             k_loss_grad<<<1, TW, 0, cs>>>(M->out, M->Tb, B, w0, w1, M->d_out, loss_hist,
                                           M->local_step);
         enqueue_backward(M, M->Xb, B, cs);
-        k_adam<<<blocks_for(N_PARAMS), TW, 0, cs>>>(M->p, M->g, M->m, M->v, N_PARAMS, lr, 0.9f, 0.999f, 1e-8f, M->step);
+        k_adam<<<blocks_for(M->n_par), TW, 0, cs>>>(M->p, M->g, M->m, M->v, M->n_par, lr, 0.9f, 0.999f, 1e-8f, M->step);
         k_steps_inc<<<1, 1, 0, cs>>>(M->step, M->local_step);
         e = hipStreamEndCapture(cs, &graph);
     }
@@ -713,9 +816,12 @@ int mhdc_mlp_grid_loss_grad(mhdc_mlp M, const float *X, const float *G, int32_t 
     if (rc)
         return rc;
     enqueue_forward(M, X, B, stream);
-    k_grid_loss_grad<<<1, TW, 0, stream>>>(M->out, G, B, M->d_out, loss, nullptr);
+    if (M->n_out == N_GRID)
+        k_score_loss_grad<<<1, TW, 0, stream>>>(M->out, G, B, M->d_out, loss, nullptr);
+    else
+        k_grid_loss_grad<<<1, TW, 0, stream>>>(M->out, G, B, M->d_out, loss, nullptr);
     enqueue_backward(M, X, B, stream);
-    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * N_PARAMS, hipMemcpyDeviceToDevice,
+    MHDC_HIP_CHECK(hipMemcpyAsync(grad, M->g, sizeof(float) * M->n_par, hipMemcpyDeviceToDevice,
                                   stream));
     return launch_ok("mlp grid loss/grad");
 }
@@ -731,7 +837,10 @@ int mhdc_mlp_decide(mhdc_mlp M, const float *X, int32_t B, double *theta, int32_
     if (rc)
         return rc;
     enqueue_forward(M, X, B, stream);
-    k_decode<<<blocks_for(B), TW, 0, stream>>>(M->out, B, theta, n_b, ok);
+    if (M->n_out == N_GRID)
+        k_decode_scores<<<blocks_for(B), TW, 0, stream>>>(M->out, B, theta, n_b, ok);
+    else
+        k_decode<<<blocks_for(B), TW, 0, stream>>>(M->out, B, theta, n_b, ok);
     return launch_ok("mlp decide");
 }
 
@@ -766,7 +875,7 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
         int32_t *nbok = nullptr;
         int rc = dmalloc((void **)&feat, sizeof(float) * N_IN, "select features");
         if (!rc)
-            rc = dmalloc((void **)&o, sizeof(float) * N_OUT, "select out");
+            rc = dmalloc((void **)&o, sizeof(float) * model->n_out, "select out");
         if (!rc)
             rc = dmalloc((void **)&th, sizeof(double), "select theta");
         if (!rc)
@@ -778,7 +887,10 @@ mhdc_handle mhdc_select(int32_t n, const int32_t *rowptr, const int32_t *colind,
         double h_th = 0.6;
         int32_t h_nbok[2] = {0, 0};
         if (!rc) {
-            k_decode<<<1, 1>>>(o, 1, th, nbok, nbok + 1);
+            if (model->n_out == N_GRID)
+                k_decode_scores<<<1, 1>>>(o, 1, th, nbok, nbok + 1);
+            else
+                k_decode<<<1, 1>>>(o, 1, th, nbok, nbok + 1);
             if (hipMemcpy(&h_th, th, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(h_nbok, nbok, sizeof(h_nbok), hipMemcpyDeviceToHost) != hipSuccess)
                 rc = set_error(MHDC_ERR_HIP, "select: reading the decision failed");

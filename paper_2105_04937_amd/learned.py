@@ -17,6 +17,14 @@ theta = 0.6; Sec. 6.4.3) and leaves their choice open (Sec. 7).  Here:
   between the grid points (grid_of(); mhdc_mlp_train_grid).  Regressing on
   the arg-min alone averages between distant near-best points; the grid
   loss lets each matrix pull the output towards wherever its time is low.
+* train --scorer: the 40-output scorer (one estimate of the log time ratio
+  per grid point; mhdc_mlp_create_scorer) is trained on the same grids with
+  its weighted squared error (mhdc_mlp_train_grid), on inputs standardised
+  with the training set's feature means and deviations; the standardisation
+  is then folded into the first layer (W1 / sd, b1 - (W1 / sd) mu), so the
+  stored network reads the library's raw features.  Its decision is the
+  grid point of the smallest estimate: unlike a single (theta, log2 n_b)
+  output it can keep apart several distant near-best regions.
 * evaluate: the network's decisions (mhdc_mlp_decide) are looked up in the
   measured grid of held-out matrices, after the byte-model judge that
   mhdc_select applies, and compared with the exhaustive best and the policy.
@@ -155,14 +163,15 @@ def target(rec, prior, eps=0.02):
     return np.array([th[i], lb[i]], np.float32)
 
 
-def init_params(seed):
-    """He-uniform weights, zero biases (the order of the C-ABI parameter
-    vector: W1 128x66, b1, W2 128x128, b2, W3 2x128, b3)."""
+def init_params(seed, n_out=2, scale=math.sqrt(6.0)):
+    """Uniform weights in +-scale / sqrt(fan_in) (He-uniform by default),
+    zero biases (the order of the C-ABI parameter vector: W1 128x66, b1, W2
+    128x128, b2, W3 n_out x 128, b3)."""
     rng = np.random.default_rng(seed)
     parts = []
-    for shape in ((128, 66), (128,), (128, 128), (128,), (2, 128), (2,)):
+    for shape in ((128, 66), (128,), (128, 128), (128,), (n_out, 128), (n_out,)):
         if len(shape) == 2:
-            lim = math.sqrt(6.0 / shape[1])
+            lim = scale / math.sqrt(shape[1])
             parts.append(rng.uniform(-lim, lim, size=shape).ravel())
         else:
             parts.append(np.zeros(shape))
@@ -200,6 +209,51 @@ def train(recs, steps=8000, B=128, lr=1e-3, seed=0, warm=500):
     h1 = net.train_grid(Xd, Gd, od(warm, s1), s1 - warm, B, lr)
     h2 = net.train_grid(Xd, Gd, od(s1, steps), steps - s1, B, lr / 3)
     return net, np.concatenate([h.cpu().numpy() for h in (h0, h1, h2)]), prior
+
+
+def fold_standardisation(params, mu, sd):
+    """Parameters of the network that, on raw features x, computes what
+    `params` computes on (x - mu) / sd: W1' = W1 / sd (per input column),
+    b1' = b1 - W1' mu; the other layers unchanged.  FP64, stored as FP32."""
+    p = np.asarray(params, np.float64).copy()
+    W1 = p[:128 * 66].reshape(128, 66) / np.asarray(sd, np.float64)[None, :]
+    b1 = p[128 * 66:128 * 66 + 128] - W1 @ np.asarray(mu, np.float64)
+    p[:128 * 66] = W1.ravel()
+    p[128 * 66:128 * 66 + 128] = b1
+    return p.astype(np.float32)
+
+
+def train_scorer(recs, steps=8000, B=128, lr=1e-3, seed=0):
+    """The 40-output scorer on the library's kernels: weights uniform in
+    +-1/sqrt(fan_in), Adam with the scorer loss (mhdc_mlp_train_grid) on
+    standardised features, lr for the first 3/4 of the steps and lr/3 for
+    the rest, then the standardisation folded into the first layer.  Returns
+    (network on raw features, loss history, (mu, sd)).  The loss weights
+    (exp(-g / 0.1) + 0.05), this initialisation and the step count were
+    chosen on a validation split of the training matrices (400 of them,
+    trained on the other 2,000), not on the held-out files."""
+    import torch
+
+    from paper_2105_04937_amd import mhdc
+    X = np.array([r["features"] for r in recs], np.float32)
+    mu = X.mean(axis=0, dtype=np.float64)
+    sd = X.std(axis=0, dtype=np.float64) + 1e-6
+    Xs = ((X - mu) / sd).astype(np.float32)
+    G = np.stack([grid_of(r) for r in recs]).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    per = []
+    while sum(len(p) for p in per) < steps * B:
+        per.append(rng.permutation(len(recs)))
+    order = np.concatenate(per)[:steps * B].astype(np.int32)
+    net = mhdc.MLP(init_params(seed, mhdc.GRID_POINTS, scale=1.0))
+    Xd, Gd = (torch.from_numpy(a).cuda() for a in (Xs, G))
+    s1 = (3 * steps) // 4
+    od = lambda a, b: torch.from_numpy(order[a * B:b * B]).cuda()  # noqa: E731
+    h1 = net.train_grid(Xd, Gd, od(0, s1), s1, B, lr)
+    h2 = net.train_grid(Xd, Gd, od(s1, steps), steps - s1, B, lr / 3)
+    folded = mhdc.MLP(fold_standardisation(net.params(), mu, sd))
+    net.close()
+    return folded, np.concatenate([h.cpu().numpy() for h in (h1, h2)]), (mu, sd)
 
 
 def evaluate(net, recs, tolerance=JUDGE_TOLERANCE):
@@ -296,6 +350,8 @@ def main(argv=None):
     t.add_argument("--test", nargs="+", required=True)
     t.add_argument("--steps", type=int, default=8000)
     t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--scorer", action="store_true",
+                   help="train the 40-output scorer instead of the 2-output network")
     t.add_argument("--out-dir", required=True)
     e = sub.add_parser("evaluate", help="re-evaluate stored weights (no training)")
     e.add_argument("--data", nargs="+", required=True)
@@ -315,22 +371,35 @@ def main(argv=None):
             with open(a.out) as f:
                 old = json.load(f)
             meta = {k: old[k] for k in ("train_steps", "train_seconds", "loss_first",
-                                         "loss_last") if k in old}
+                                         "loss_last", "network", "train_loss",
+                                         "train_warm_steps") if k in old}
         rep = report(load_network(a.weights), recs, test, a.test, meta)
         with open(a.out, "w") as f:
             json.dump(rep, f, indent=1)
         print(json.dumps(rep))
         return
     t0 = time.time()
-    net, hist, prior = train(recs, steps=a.steps, lr=a.lr)
+    if a.scorer:
+        net, hist, _ = train_scorer(recs, steps=a.steps, lr=a.lr)
+        meta = dict(network="scorer: 66 -> 128 -> 128 -> 40, one estimate of log(t / t_best) "
+                            "per grid point, decision = the point of the smallest estimate; "
+                            "weights uniform in +-1/sqrt(fan_in) at the start",
+                    train_loss="scorer loss (weighted squared error per grid point, weight "
+                               "exp(-g / 0.1) + 0.05) on standardised features, "
+                               "standardisation folded into the first layer")
+    else:
+        net, hist, _ = train(recs, steps=a.steps, lr=a.lr)
+        meta = dict(network="66 -> 128 -> 128 -> 2, output (theta, log2 n_b)",
+                    train_warm_steps=500,
+                    train_loss="squared error to the arg-min for the warm-up steps, then "
+                               "the grid loss")
     dt = time.time() - t0
     os.makedirs(a.out_dir, exist_ok=True)
     np.save(os.path.join(a.out_dir, "weights.npy"), net.params())
     rep = report(net, recs, test, a.test,
-                 dict(train_steps=a.steps, train_seconds=round(dt, 2), train_warm_steps=500,
-                      train_loss="squared error to the arg-min for the warm-up steps, then "
-                                 "the grid loss",
-                      loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean())))
+                 dict(train_steps=a.steps, train_seconds=round(dt, 2),
+                      loss_first=float(hist[:20].mean()), loss_last=float(hist[-20:].mean()),
+                      **meta))
     with open(os.path.join(a.out_dir, "eval_report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep))

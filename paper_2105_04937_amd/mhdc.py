@@ -76,6 +76,7 @@ class SelectResult(ctypes.Structure):
 
 
 MLP_PARAMS = 25346
+MLP_SCORER_PARAMS = 30248  # the 40-output scorer (one output per grid point)
 MLP_IN = 66
 GRID_POINTS = 40  # theta 0.5 .. 0.9 x n_b 32 .. 4096
 
@@ -133,6 +134,8 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_float)]),
     "mhdc_features": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp]),
     "mhdc_mlp_create": (_vp, [_vp]),
+    "mhdc_mlp_create_scorer": (_vp, [_vp]),
+    "mhdc_mlp_outputs": (_i32, [_vp]),
     "mhdc_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
     "mhdc_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "mhdc_mlp_forward_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
@@ -530,20 +533,26 @@ def features(rowptr, colind, val, stream=None):
 
 
 class MLP:
-    """The 66 -> 128 -> 128 -> 2 selector network on the device."""
+    """The 66 -> 128 -> 128 -> 2 selector network on the device, or the
+    40-output scorer when given MLP_SCORER_PARAMS parameters."""
 
     def __init__(self, params):
         import numpy as np
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
-        if p.size != MLP_PARAMS:
-            raise ValueError("expected %d parameters" % MLP_PARAMS)
-        self._h = lib().mhdc_mlp_create(p.ctypes.data_as(ctypes.c_void_p))
+        if p.size == MLP_PARAMS:
+            self._h = lib().mhdc_mlp_create(p.ctypes.data_as(ctypes.c_void_p))
+        elif p.size == MLP_SCORER_PARAMS:
+            self._h = lib().mhdc_mlp_create_scorer(p.ctypes.data_as(ctypes.c_void_p))
+        else:
+            raise ValueError("expected %d or %d parameters" % (MLP_PARAMS, MLP_SCORER_PARAMS))
         if not self._h:
             _raise()
+        self.outputs = lib().mhdc_mlp_outputs(self._h)
+        self.n_params = p.size
 
     def params(self):
         import numpy as np
-        p = np.empty(MLP_PARAMS, np.float32)
+        p = np.empty(self.n_params, np.float32)
         _check(lib().mhdc_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
         return p
 
@@ -555,17 +564,17 @@ class MLP:
 
     def forward(self, X, stream=None):
         B = self._rows(X)
-        out = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+        out = torch.empty((B, self.outputs), dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_forward(self._h, _dptr(X, torch.float32, "X"), B,
                                       _dptr(out, torch.float32, "out"), _stream(stream)))
         return out
 
     def forward_noalloc(self, X, out, stream=None):
         """mhdc_mlp_forward_noalloc: the forward pass into a caller-provided
-        (B, 2) float32 output, with no device allocation in the library."""
+        (B, outputs) float32 output, with no device allocation in the library."""
         B = self._rows(X)
-        if tuple(out.shape) != (B, 2):
-            raise ValueError("out must have shape (B, 2)")
+        if tuple(out.shape) != (B, self.outputs):
+            raise ValueError("out must have shape (B, %d)" % self.outputs)
         _check(lib().mhdc_mlp_forward_noalloc(self._h, _dptr(X, torch.float32, "X"), B,
                                               _dptr(out, torch.float32, "out"), _stream(stream)))
         return out
@@ -574,7 +583,7 @@ class MLP:
         if tuple(T.shape) != (self._rows(X), 2):
             raise ValueError("T must have shape (B, 2)")
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
-        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_loss_grad(self._h, _dptr(X, torch.float32, "X"),
                                         _dptr(T, torch.float32, "T"), X.shape[0], float(w[0]),
                                         float(w[1]), _dptr(loss, torch.float32, "loss"),
@@ -601,7 +610,7 @@ class MLP:
         if tuple(G.shape) != (self._rows(X), GRID_POINTS):
             raise ValueError("G must have shape (B, %d)" % GRID_POINTS)
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
-        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
         _check(lib().mhdc_mlp_grid_loss_grad(self._h, _dptr(X, torch.float32, "X"),
                                              _dptr(G, torch.float32, "G"), X.shape[0],
                                              _dptr(loss, torch.float32, "loss"),

@@ -280,3 +280,105 @@ def test_select_refine_tiny_matrices():
         assert_oracle_bits(h.spmv(torch.from_numpy(x).cuda()), oracle.mhdc_spmv(ref, x),
                            "tiny refined")
         h.close()
+
+
+# ------------------------------------------------------------------ scorer
+def _scorer_params(seed, noise=0.05):
+    rng = np.random.default_rng(seed)
+    p = S.init_params(seed, S.N_SCORES)
+    return (p + rng.normal(0, noise, p.size)).astype(np.float32)
+
+
+def test_scorer_forward_loss_gradient_match_oracle():
+    """The 40-output scorer through the C-ABI: forward pass, scorer loss and
+    gradient against the FP64 oracle; the squared error to 2 targets is not
+    offered for it."""
+    say("case: scorer forward / loss / gradient")
+    rng = np.random.default_rng(12)
+    p = _scorer_params(2)
+    net = mhdc.MLP(p)
+    assert net.outputs == 40 and net.params().size == S.N_PARAMS_SCORER
+    assert np.array_equal(net.params().view(np.int32), p.view(np.int32))
+    for B in (1, 37, 128):
+        X = rng.uniform(0, 1, size=(B, 66)).astype(np.float32)
+        G = rng.uniform(0.0, 0.5, size=(B, 40)).astype(np.float32)
+        G[:, 3] = 0.0
+        Xd, Gd = torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda()
+        out = net.forward(Xd).cpu().numpy()
+        ref, _ = S.forward(p, X)
+        assert out.shape == (B, 40) and np.allclose(out, ref, rtol=1e-5, atol=1e-5)
+        loss, g = net.grid_loss_grad(Xd, Gd)
+        L, gref = S.score_loss_and_grad(p.astype(np.float64), X, G)
+        assert abs(loss.item() - L) <= 1e-5 * max(1.0, abs(L)), (loss.item(), L)
+        g = g.cpu().numpy()
+        assert g.size == S.N_PARAMS_SCORER
+        assert np.allclose(g, gref, rtol=1e-3, atol=1e-5 * np.abs(gref).max())
+        o2 = torch.empty((B, 40), dtype=torch.float32, device="cuda")
+        net.forward_noalloc(Xd, o2)
+        assert np.array_equal(o2.cpu().numpy().view(np.int32), out.view(np.int32))
+    with pytest.raises(mhdc.MhdcError) as ei:
+        net.loss_grad(Xd, torch.zeros((B, 2), dtype=torch.float32, device="cuda"))
+    assert ei.value.name == "MHDC_ERR_NOT_SUPPORTED"
+    net.close()
+
+
+def test_scorer_training_matches_oracle_adam_and_is_deterministic():
+    say("case: scorer training")
+    rng = np.random.default_rng(13)
+    N, B, steps, lr = 200, 32, 5, 1e-3
+    X = rng.uniform(0, 1, size=(N, 66)).astype(np.float32)
+    G = rng.uniform(0.0, 0.4, size=(N, 40)).astype(np.float32)
+    order = np.concatenate([rng.permutation(N)[:B] for _ in range(steps)]).astype(np.int32)
+    p0 = _scorer_params(14)
+    Xd, Gd, od = (torch.from_numpy(a).cuda() for a in (X, G, order))
+    net = mhdc.MLP(p0)
+    hist = net.train_grid(Xd, Gd, od, steps, B, lr).cpu().numpy()
+    p_gpu = net.params()
+    p = p0.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(steps):
+        idx = order[t * B:(t + 1) * B]
+        L, g = S.score_loss_and_grad(p, X[idx], G[idx])
+        assert abs(hist[t] - L) <= 1e-4 * max(1.0, L)
+        p, m, v = S.adam(p, g, m, v, t + 1, lr)
+    d = np.abs(p_gpu - p)
+    assert d.max() <= 2 * steps * lr
+    assert np.quantile(d, 0.99) <= 1e-5
+    net2 = mhdc.MLP(p0)
+    net2.train_grid(Xd, Gd, od, steps, B, lr)
+    assert np.array_equal(net2.params().view(np.int32), p_gpu.view(np.int32))
+    with pytest.raises(mhdc.MhdcError) as ei:
+        net2.train(Xd, torch.zeros((N, 2), dtype=torch.float32, device="cuda"), od, steps, B, lr)
+    assert ei.value.name == "MHDC_ERR_NOT_SUPPORTED"
+
+
+def test_scorer_decide_and_select():
+    """decide takes the grid point of the smallest output, as the oracle's
+    decode_scores does on the oracle's forward pass; mhdc_select builds the
+    handle of a constant scorer's point (judge permitting)."""
+    say("case: scorer decide / select")
+    rng = np.random.default_rng(15)
+    p = _scorer_params(16, noise=0.2)
+    net = mhdc.MLP(p)
+    X = rng.uniform(0, 1, size=(300, 66)).astype(np.float32)
+    th, nb, ok = (t.cpu().numpy() for t in net.decide(torch.from_numpy(X).cuda()))
+    out = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    wth, wnb, wok = S.decode_scores(out)   # decode of the GPU's own outputs: exact
+    assert np.array_equal(th, wth) and np.array_equal(nb, wnb) and np.array_equal(ok, wok)
+    rth, rnb, _ = S.decode_scores(S.forward(p, X)[0])
+    assert np.mean((rth == th) & (rnb == nb)) >= 0.99   # FP32 vs FP64 near-ties aside
+    net.close()
+    # a constant scorer (b3 only) whose smallest output is (0.7, 128)
+    c = np.ones(40, np.float32)
+    c[8 * 2 + 2] = -1.0
+    q = np.zeros(S.N_PARAMS_SCORER, np.float32)
+    q[-40:] = c
+    const = mhdc.MLP(q)
+    m = synth.partially_diagonal(24, 7)
+    h, res = mhdc.select(*dev(m), model=const, tolerance=1e9)
+    assert (res["theta_net"], res["n_b_net"], res["net_ok"]) == (0.7, 128, 1)
+    assert (res["theta"], res["n_b"], res["used_rule"]) == (0.7, 128, 0)
+    assert h.info()["n_b"] == 128 and abs(h.info()["theta"] - 0.7) < 1e-12
+    h.close()
+    const.close()

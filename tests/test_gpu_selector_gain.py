@@ -1,7 +1,8 @@
 """What the trained selector gains over the paper's policy.
 
-The committed network (trained on the GPU by the library's own kernels on
-2,400 matrices) decides (theta, n_b) for the 240 held-out matrices through
+The committed network (the 40-output scorer, trained on the GPU by the
+library's own kernels on 2,400 matrices) decides (theta, n_b) for the 240
+held-out matrices through
 mhdc_mlp_decide; each decision is looked up in the SpMV times measured on
 MI355X for the whole grid (committed with the data), after the byte-model
 judge that mhdc_select applies.  Compared with the exhaustive best of the
@@ -38,8 +39,8 @@ def test_selector_gain_over_policy():
         "judge override rate %.3f" % (rep["within_5pct_network_unjudged"],
                                       rep["mean_ratio_network_unjudged"],
                                       rep["judge_override_rate"]))
-    assert rep["within_5pct_network_unjudged"] >= 0.8
-    assert rep["mean_ratio_network_unjudged"] <= 1.03
+    assert rep["within_5pct_network_unjudged"] >= 0.9
+    assert rep["mean_ratio_network_unjudged"] <= 1.025
     # the refinement is a measured search around the decision (up to six
     # more conversions and timings); it picks from a superset of the selection
     assert rep["mean_ratio_refined"] <= rep["mean_ratio_selected"]

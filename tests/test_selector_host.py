@@ -34,3 +34,4 @@ def test_refine_candidates(decision, want):
     each once and never the decision itself."""
     from paper_2105_04937_amd import mhdc
     assert mhdc.refine_candidates(*decision) == want
+
