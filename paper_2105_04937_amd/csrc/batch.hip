@@ -82,14 +82,21 @@ __device__ inline void batch_tile_rm(const BatchItem &it, int64_t local, double 
         spmv_tile_rm<WG, KC, true, true, false>(it.a, local, lds);
 }
 
-// Tiles are dealt to the 8 XCDs in runs of BATCH_RUN consecutive tiles
-// (run r belongs to XCD r mod 8), and each XCD has a tile counter of its own
+// Every item's tiles go to one XCD: the items are dealt to the 8 XCDs,
+// largest algorithmic bytes first, each to the XCD with the least so far
+// (the host's schedule, below), so the tiles that share an item's x rows --
+// its neighbours through the near diagonals and the planes its far
+// diagonals reach -- are processed under one L2.  The schedule lists each
+// XCD's tiles as (item slot << 32 | local tile) in a device array after the
+// XCDs' start indices; each XCD has a tile counter of its own
 // (BATCH_CTR_STRIDE ints apart).  Persistent workgroup w runs on XCD w mod 8
 // (a launch's workgroups are dispatched to the XCDs in turn) and takes its
-// XCD's tiles in order, so neighbouring tiles, which read the same x through
-// the near diagonals, are processed under one L2; a workgroup whose XCD has
-// run out takes the next XCD's tiles, until all eight have run out.
-constexpr int BATCH_XCDS = 8, BATCH_RUN = 16, BATCH_CTR_STRIDE = 32;
+// XCD's entries in order; a workgroup whose XCD has run out takes the next
+// XCD's, until all eight have run out.  Reading the entry also names the
+// item, so no search over the items is needed.
+constexpr int BATCH_XCDS = 8, BATCH_CTR_STRIDE = 32;
+// schedule layout: starts[0..8] at [0, 9), entries from index SCHED_HEAD
+constexpr int SCHED_HEAD = 16;
 
 __global__ void k_batch_reset(int32_t *counter)
 {
@@ -97,66 +104,57 @@ __global__ void k_batch_reset(int32_t *counter)
         counter[threadIdx.x * BATCH_CTR_STRIDE] = 0;
 }
 
-// The i-th tile of XCD x (strictly increasing in i).
-__device__ inline int64_t batch_xcd_tile(int x, int64_t i)
-{
-    const int64_t run = x + (int64_t)BATCH_XCDS * (i / BATCH_RUN);
-    return run * BATCH_RUN + i % BATCH_RUN;
-}
-
-// Next tile for this workgroup (uniform), or -1 when every XCD has run out.
-// *x is the XCD whose tiles the workgroup is taking; x0 its own.  Each
-// counter only grows, and a workgroup moves past an XCD at its first
-// exhausted answer, so every workgroup reaches -1.
-__device__ inline int64_t batch_take(int32_t *counter, int x0, int *x, int64_t total_tiles,
-                                     int64_t *s_tile)
+// Next schedule entry for this workgroup (uniform), or -1 when every XCD has
+// run out.  *x is the XCD whose entries the workgroup is taking; x0 its own;
+// s_start holds the XCDs' start indices.  Each counter only grows, and a
+// workgroup moves past an XCD at its first exhausted answer, so every
+// workgroup reaches -1.
+__device__ inline int64_t batch_take(int32_t *counter, const int64_t *__restrict__ sched,
+                                     const int64_t *s_start, int x0, int *x, int64_t *s_tile)
 {
     for (;;) {
-        if (threadIdx.x == 0)
-            *s_tile = batch_xcd_tile(*x, atomicAdd(&counter[*x * BATCH_CTR_STRIDE], 1));
+        if (threadIdx.x == 0) {
+            const int64_t i = s_start[*x] + atomicAdd(&counter[*x * BATCH_CTR_STRIDE], 1);
+            *s_tile = i < s_start[*x + 1] ? sched[SCHED_HEAD + i] : -1;
+        }
         __syncthreads();
-        const int64_t t = *s_tile;
+        const int64_t e = *s_tile;
         __syncthreads();
-        if (t < total_tiles)
-            return t;
+        if (e >= 0)
+            return e;
         *x = (*x + 1) & (BATCH_XCDS - 1);
         if (*x == x0)
             return -1;
     }
 }
 
-// Item owning global tile t: the last item with tile_begin <= t.
-__device__ inline int32_t batch_item_of(const BatchItem *__restrict__ items, int32_t count,
-                                        int64_t t)
+// The XCDs' start indices of the schedule, staged in LDS once per workgroup.
+__device__ inline void batch_load_starts(const int64_t *__restrict__ sched, int64_t *s_start)
 {
-    int32_t lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (uniform_load(&items[mid].tile_begin, 0) <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
+    if (threadIdx.x <= BATCH_XCDS)
+        s_start[threadIdx.x] = sched[threadIdx.x];
+    __syncthreads();
 }
 
 // Four waves per SIMD (at most 128 VGPRs): uncapped, the compiler took 132
 // and the machine held three 256-lane workgroups per CU, which measured 6%
 // slower on a 64-matrix batch.
 template <int WG>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(const BatchItem *__restrict__ items, int32_t count,
-                                              int64_t total_tiles, int32_t *counter)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(const BatchItem *__restrict__ items,
+                                              const int64_t *__restrict__ sched, int32_t *counter)
 {
     __shared__ double s_prod[batch_lds_doubles<WG>()];
     __shared__ int64_t s_tile;
+    __shared__ int64_t s_start[BATCH_XCDS + 1];
+    batch_load_starts(sched, s_start);
     const int x0 = blockIdx.x & (BATCH_XCDS - 1);
     int x = x0;
     for (;;) {
-        const int64_t t = batch_take(counter, x0, &x, total_tiles, &s_tile);
-        if (t < 0)
+        const int64_t e = batch_take(counter, sched, s_start, x0, &x, &s_tile);
+        if (e < 0)
             break;
-        const BatchItem &it = items[batch_item_of(items, count, t)];
-        const int64_t local = t - it.tile_begin;
+        const BatchItem &it = items[e >> 32];
+        const int64_t local = e & 0xffffffffLL;
         switch (it.kc) {
         case 1: batch_tile<WG, 1>(it, local, s_prod); break;
         case 2: batch_tile<WG, 2>(it, local, s_prod); break;
@@ -171,21 +169,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // row.  Kernels of their own: the tile routine keeps KC/2 rows per lane in
 // registers and would not fit the column-major kernel's register cap.
 template <int WG>
-__device__ inline void batch_rm_loop(const BatchItem *__restrict__ items, int32_t count,
-                                     int64_t total_tiles, int32_t *counter)
+__device__ inline void batch_rm_loop(const BatchItem *__restrict__ items,
+                                     const int64_t *__restrict__ sched, int32_t *counter)
 {
     __shared__ double s_prod[(TileShapeRm<WG, 2>::LDS_BYTES + 7) / 8];
     static_assert(TileShapeRm<WG, 2>::LDS_BYTES == TileShapeRm<WG, 16>::LDS_BYTES,
                   "one LDS size for every width");
     __shared__ int64_t s_tile;
+    __shared__ int64_t s_start[BATCH_XCDS + 1];
+    batch_load_starts(sched, s_start);
     const int x0 = blockIdx.x & (BATCH_XCDS - 1);
     int x = x0;
     for (;;) {
-        const int64_t t = batch_take(counter, x0, &x, total_tiles, &s_tile);
-        if (t < 0)
+        const int64_t e = batch_take(counter, sched, s_start, x0, &x, &s_tile);
+        if (e < 0)
             break;
-        const BatchItem &it = items[batch_item_of(items, count, t)];
-        const int64_t local = t - it.tile_begin;
+        const BatchItem &it = items[e >> 32];
+        const int64_t local = e & 0xffffffffLL;
         switch (it.kc) {
         case 2: batch_tile_rm<WG, 2>(it, local, s_prod); break;
         case 4: batch_tile_rm<WG, 4>(it, local, s_prod); break;
@@ -197,18 +197,18 @@ __device__ inline void batch_rm_loop(const BatchItem *__restrict__ items, int32_
 
 // 64 lanes: one wave per SIMD (LDS-bound).
 __global__ __launch_bounds__(64) void k_batch_rm64(const BatchItem *__restrict__ items,
-                                                   int32_t count, int64_t total_tiles,
+                                                   const int64_t *__restrict__ sched,
                                                    int32_t *counter)
 {
-    batch_rm_loop<64>(items, count, total_tiles, counter);
+    batch_rm_loop<64>(items, sched, counter);
 }
 
 // 256 lanes: held to three waves per SIMD (at most 168 VGPRs, no spills;
 // uncapped the compiler took 170 and only two fitted).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_batch_rm256(
-    const BatchItem *__restrict__ items, int32_t count, int64_t total_tiles, int32_t *counter)
+    const BatchItem *__restrict__ items, const int64_t *__restrict__ sched, int32_t *counter)
 {
-    batch_rm_loop<256>(items, count, total_tiles, counter);
+    batch_rm_loop<256>(items, sched, counter);
 }
 
 }  // namespace
@@ -226,6 +226,7 @@ struct mhdc_batch_s {
     std::vector<BatchItem> host_items;
     BatchItem *d_items = nullptr;
     int32_t *d_counter = nullptr;
+    int64_t *d_sched = nullptr;  // XCD starts, then (slot << 32 | local tile) entries
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double flops = 0, bytes_alg = 0;
@@ -262,9 +263,51 @@ int batch_grid(int wg, int rowmajor, int64_t total_tiles, int32_t *grid)
 // 256 CUs x 32 resident workgroups).
 constexpr int64_t BATCH_MAX_TILES = (int64_t)INT32_MAX - (1LL << 20);
 
+void drop_graph(mhdc_batch_s *b);
+
+// The XCD schedule (see batch_take): items dealt to the XCDs by descending
+// work (algorithmic bytes), each to the least-loaded XCD (the first on
+// ties); each XCD's entries list its items' tiles in slot order.
+void build_schedule(const std::vector<int64_t> &tiles_of, const std::vector<double> &work,
+                    std::vector<int64_t> *sched)
+{
+    const int32_t count = (int32_t)tiles_of.size();
+    std::vector<int32_t> by_work(count);
+    for (int32_t i = 0; i < count; i++)
+        by_work[i] = i;
+    std::stable_sort(by_work.begin(), by_work.end(),
+                     [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+    std::vector<int32_t> xcd_of(count, 0);
+    double load[BATCH_XCDS] = {};
+    for (int32_t slot : by_work) {
+        int x = 0;
+        for (int y = 1; y < BATCH_XCDS; y++)
+            if (load[y] < load[x])
+                x = y;
+        xcd_of[slot] = x;
+        load[x] += work[slot];
+    }
+    int64_t total = 0;
+    for (int64_t t : tiles_of)
+        total += t;
+    sched->assign((size_t)(SCHED_HEAD + total), 0);
+    int64_t pos = 0;
+    for (int x = 0; x < BATCH_XCDS; x++) {
+        (*sched)[x] = pos;
+        for (int32_t slot = 0; slot < count; slot++)
+            if (xcd_of[slot] == x)
+                for (int64_t l = 0; l < tiles_of[slot]; l++)
+                    (*sched)[SCHED_HEAD + pos++] = ((int64_t)slot << 32) | l;
+    }
+    (*sched)[BATCH_XCDS] = pos;
+}
+
 // Build the descriptor table for an X/Y binding and workgroup size, upload
 // it, and only then take it over into the batch: a failure leaves the batch
-// with its previous binding, workgroup size and grid, still runnable.
+// with its previous binding, workgroup size and grid, still runnable.  The
+// XCD schedule depends on the workgroup size only (the items' tiles and
+// bytes): it is rebuilt into a new buffer when that changes, and kept
+// otherwise.
 int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int64_t *ldx,
                  double *const *Y, const int64_t *ldy)
 {
@@ -281,6 +324,8 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
         return b->mats[x]->n > b->mats[y]->n;
     });
     std::vector<BatchItem> items(b->count, BatchItem{});
+    std::vector<int64_t> tiles_of(b->count);
+    std::vector<double> work(b->count);
     int64_t tiles = 0;
     double flops = 0, bytes = 0;
     for (int32_t slot = 0; slot < b->count; slot++) {
@@ -300,9 +345,11 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
         it.rg = (b->rowmajor ? rm_row_gather(m) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
         it.a.pairs = b->rowmajor && rm_pairs(X[i], lx, Y[i], ly) ? 1 : 0;
         it.tile_begin = tiles;
-        tiles += ((int64_t)m.n + wg - 1) / wg;
+        tiles_of[slot] = ((int64_t)m.n + wg - 1) / wg;
+        tiles += tiles_of[slot];
         flops += 2.0 * (double)m.nnz * k;
-        bytes += format_bytes(m) + 16.0 * (double)m.n * k;
+        work[slot] = format_bytes(m) + 16.0 * (double)m.n * k;
+        bytes += work[slot];
     }
     if (tiles > BATCH_MAX_TILES)
         return set_error(MHDC_ERR_SIZE, "too many tiles in the batch");
@@ -310,8 +357,29 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
     int rc = batch_grid(wg, b->rowmajor, tiles, &grid);
     if (rc)
         return rc;
-    MHDC_HIP_CHECK(hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * b->count,
-                             hipMemcpyHostToDevice));
+    int64_t *nd = nullptr;
+    if (!(b->d_sched && wg == b->wg && tiles == b->total_tiles)) {
+        std::vector<int64_t> sched;
+        build_schedule(tiles_of, work, &sched);
+        if ((rc = dmalloc((void **)&nd, sizeof(int64_t) * sched.size(), "batch schedule")))
+            return rc;
+        if (hipMemcpy(nd, sched.data(), sizeof(int64_t) * sched.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            dfree(nd);
+            return set_error(MHDC_ERR_HIP, "batch schedule upload failed");
+        }
+    }
+    if (hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * b->count,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        dfree(nd);
+        return set_error(MHDC_ERR_HIP, "batch descriptor upload failed");
+    }
+    if (nd) {
+        // a captured graph holds the old schedule's address
+        drop_graph(b);
+        dfree(b->d_sched);
+        b->d_sched = nd;
+    }
     b->host_items.swap(items);
     b->wg = wg;
     b->total_tiles = tiles;
@@ -327,14 +395,13 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
         return MHDC_OK;
     k_batch_reset<<<1, 64, 0, s>>>(b->d_counter);
     if (b->rowmajor && b->wg == 64)
-        k_batch_rm64<<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+        k_batch_rm64<<<b->grid, 64, 0, s>>>(b->d_items, b->d_sched, b->d_counter);
     else if (b->rowmajor)
-        k_batch_rm256<<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles,
-                                              b->d_counter);
+        k_batch_rm256<<<b->grid, 256, 0, s>>>(b->d_items, b->d_sched, b->d_counter);
     else if (b->wg == 64)
-        k_batch<64><<<b->grid, 64, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+        k_batch<64><<<b->grid, 64, 0, s>>>(b->d_items, b->d_sched, b->d_counter);
     else
-        k_batch<256><<<b->grid, 256, 0, s>>>(b->d_items, b->count, b->total_tiles, b->d_counter);
+        k_batch<256><<<b->grid, 256, 0, s>>>(b->d_items, b->d_sched, b->d_counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(MHDC_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(e));
@@ -344,6 +411,10 @@ int enqueue(mhdc_batch_s *b, hipStream_t s)
 mhdc_batch batch_create(int32_t count, const mhdc_handle *mats, const int32_t *nrhs,
                         const double *const *X, const int64_t *ldx, double *const *Y,
                         const int64_t *ldy, int32_t wg_size, int32_t rowmajor);
+
+}  // namespace
+
+namespace {
 
 void drop_graph(mhdc_batch_s *b)
 {
@@ -417,6 +488,7 @@ mhdc_batch batch_create(int32_t count, const mhdc_handle *mats, const int32_t *n
     if (rc) {
         dfree(b->d_items);
         dfree(b->d_counter);
+        dfree(b->d_sched);
         delete b;
         return nullptr;
     }
@@ -526,6 +598,7 @@ void mhdc_batch_destroy(mhdc_batch b)
     drop_graph(b);
     dfree(b->d_items);
     dfree(b->d_counter);
+    dfree(b->d_sched);
     delete b;
 }
 
