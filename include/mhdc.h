@@ -252,10 +252,11 @@ int mhdc_stream_indirect(int64_t N, const double *A, const double *B,
  * blocks for the threads (Secs. 6.4.2-6.4.3, matrix #17).  All tiles of
  * all items form one sequence (items with more right-hand sides first, so
  * the launch ends on its cheapest tiles); a persistent grid of (CUs x
- * resident workgroups) takes tiles until none is left, each XCD from a
- * counter of its own over runs of 16 consecutive tiles dealt to the XCDs in
- * turn (neighbouring tiles share x through their near diagonals and then
- * share an L2), taking other XCDs' tiles once its own have run out.  Each
+ * resident workgroups) takes tiles until none is left.  Each item's tiles
+ * go to one XCD (items dealt by descending bytes to the least-loaded XCD),
+ * so the tiles sharing an item's x rows share an L2; each XCD takes its
+ * tiles from a counter of its own and then other XCDs' tiles once its own
+ * have run out.  Each
  * tile writes only its own rows, so item i's result is bit-identical to
  * mhdc_spmm(mats[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i]).
  *

@@ -1,9 +1,9 @@
 // batch.hip -- many M-HDC / HDC / CSR products in one persistent launch.
 //
 // A batch holds up to thousands of (matrix, right-hand-side block) items of
-// uneven sizes.  The tiles of all items are numbered in one sequence; a
-// persistent grid sized to the machine (CUs x resident workgroups) takes
-// tiles from per-XCD atomic counters until the sequence is exhausted, so
+// uneven sizes.  The tiles of all items are dealt to the XCDs item by item;
+// a persistent grid sized to the machine (CUs x resident workgroups) takes
+// tiles from per-XCD atomic counters until every XCD's list is exhausted, so
 // small matrices never leave CUs idle the way one launch per matrix does.
 // Each tile writes only its own rows (no floating-point atomics): the result
 // of every item is bit-identical to its single-matrix launch.
