@@ -164,6 +164,36 @@ def test_batch_tune_and_errors(batch_case):
     b.close()
 
 
+def test_batch_schedule_small_counts_and_rebuild(batch_case):
+    """Batches of fewer members than XCDs (the XCDs without members take
+    others' tiles from the start) and one of more: every tile is taken
+    exactly once (outputs start as NaN) and every member equals its single
+    launch and the oracle.  A workgroup-size change replaces the schedule:
+    graph replays before and after it, and back, give the same results."""
+    items, mats, Xs, refs, _ = batch_case
+    for sel in ([0], [6, 8, 9], list(range(9))):
+        say("case: batch schedule, members %s" % sel)
+        its = [items[i] for i in sel]
+        Ys = [torch.full_like(Xs[i], float("nan")) for i in sel]
+        b = mhdc.Batch([mats[i] for i in sel], [Xs[i] for i in sel], Ys=Ys)
+        b.run()
+        _check_items(its, [mats[i] for i in sel], [Xs[i] for i in sel], Ys, [refs[i] for i in sel])
+        b.close()
+    say("case: batch schedule rebuilt by set_wg under graph replay")
+    Ys = [torch.full_like(X, float("nan")) for X in Xs]
+    b = mhdc.Batch(mats, Xs, Ys=Ys)
+    b.graph_launch()
+    _check_items(items, mats, Xs, Ys, refs)
+    for wg in (64, 256):
+        b.set_wg(wg)
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        b.graph_launch()
+        b.graph_launch()
+        _check_items(items, mats, Xs, Ys, refs)
+    b.close()
+
+
 @pytest.mark.parametrize("k", [1, 4])
 def test_autotune(k):
     m = synth.partially_diagonal(40, 17, drop=0.15)
