@@ -58,7 +58,10 @@ DATA_DIR = os.path.join(HERE, "selector_data")
 
 
 JUDGE_TOLERANCE = 0.25      # mhdc_select keeps a proposal up to 1.25 x the policy's V
-WEIGHTS = os.path.join(DATA_DIR, "weights.npy")
+WEIGHTS = os.path.join(DATA_DIR, "weights.npy")  # the 40-output scorer (the default)
+# the 66 -> 128 -> 128 -> 2 network with output (theta, log2 n_b), trained with
+# the grid loss; its held-out report is eval_report_theta_nb.json
+WEIGHTS_THETA_NB = os.path.join(DATA_DIR, "weights_theta_nb.npy")
 
 
 def key(theta, nb):
@@ -66,7 +69,8 @@ def key(theta, nb):
 
 
 def load_network(path=WEIGHTS):
-    """The trained selector network (parameters stored as float32 .npy)."""
+    """A trained selector network (parameters stored as float32 .npy; the
+    kind, scorer or 2-output, follows from the parameter count)."""
     from paper_2105_04937_amd import mhdc
     return mhdc.MLP(np.load(path, allow_pickle=False))
 

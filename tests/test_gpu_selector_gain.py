@@ -79,3 +79,21 @@ def test_select_end_to_end_with_trained_network():
         ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, r["n_b"], r["theta"])
         assert_oracle_bits(h.spmv(torch.from_numpy(x).cuda()), oracle.mhdc_spmv(ref, x),
                            "selected theta=%g n_b=%d" % (r["theta"], r["n_b"]))
+
+
+def test_theta_nb_network_gain_over_policy():
+    """The stored 66 -> 128 -> 128 -> 2 network (output theta, log2 n_b;
+    grid loss) on the same held-out matrices: better than the policy, and
+    its figures are those of its committed report."""
+    import json
+    recs = learned.load(TEST)
+    net = learned.load_network(learned.WEIGHTS_THETA_NB)
+    assert net.outputs == 2
+    rep, _ = learned.evaluate(net, recs, tolerance=learned.JUDGE_TOLERANCE)
+    say("2-output network: within 5%% %.3f, mean t/t_best %.4f" % (
+        rep["within_5pct_network_unjudged"], rep["mean_ratio_network_unjudged"]))
+    with open(os.path.join(learned.DATA_DIR, "eval_report_theta_nb.json")) as f:
+        stored = json.load(f)
+    assert rep["within_5pct_network_unjudged"] == stored["within_5pct_network_unjudged"]
+    assert rep["within_5pct_network_unjudged"] >= 0.8
+    assert rep["mean_ratio_selected"] < rep["mean_ratio_rule"]
