@@ -21,17 +21,21 @@ int32_t xcd_run(int32_t far_offset, int32_t tile_rows)
     // A tile's rows [t*T, t*T + T) read x through the diagonal at +D in tiles
     // t + D/T and t + D/T + 1 (rows weighted by how much of the window each
     // holds); with runs of C tiles per XCD, tile u sits on XCD (u / C) mod 8.
-    // Score each C in [8, 16] by the share of those rows on the tile's own
-    // XCD over one round of 8*C tiles; ties go to the longer run (near
+    // Score each C whose runs hold 2048 to 4096 rows (8..16 tiles of 256
+    // rows, 4..8 of 512) by the share of those rows on the tile's own XCD
+    // over one round of 8*C tiles; ties go to the longer run (near
     // neighbours in the same L2).  192^3 27-point stencil (D = N^2 + N + 1 =
     // 37,057, T = 256): C = 9 (144 tiles = 16 runs), 442 against 460 us at
-    // C = 16 for one right-hand side; 256^3 7-point (D = 65,536): C = 16.
+    // C = 16 for one right-hand side; 256^3 7-point (D = 65,536): C = 16,
+    // or 8 for 512-row tiles.
+    const int32_t c_hi = tile_rows > 0 && 4096 / tile_rows >= 2 ? 4096 / tile_rows : 2;
+    const int32_t c_lo = c_hi / 2;
     if (far_offset <= 0 || tile_rows <= 0)
-        return 16;
+        return c_hi;
     const int64_t d0 = far_offset / tile_rows, part = far_offset % tile_rows;
-    int32_t best = 16;
+    int32_t best = c_hi;
     int64_t best_score = -1;
-    for (int32_t c = 16; c >= 8; c--) {
+    for (int32_t c = c_hi; c >= c_lo; c--) {
         int64_t score = 0;  // rows on the own XCD, summed over one round
         for (int64_t t = 0; t < 8 * c; t++) {
             const int64_t x = (t / c) % 8;
@@ -152,6 +156,7 @@ H *finish(H *h, int rc)
     // it the staged products measured faster on the selector's matrices
     h->m.launch = default_launch(h->m.n, h->m.n_b, h->m.nnz, h->m.K > 0 ? 0.0 : h->m.row_repeat,
                                  h->m.far_offset);
+    h->m.dflt = h->m.launch;
     return h;
 }
 

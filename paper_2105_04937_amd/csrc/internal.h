@@ -42,6 +42,9 @@ struct BdcMatrix {
     int32_t far_offset = 0;
     int device = 0;
     mhdc_launch launch{2, 256, 0, 0, 0};
+    // the launch the conversion chose (launch differs once the caller or
+    // the autotuner sets one)
+    mhdc_launch dflt{2, 256, 0, 0, 0};
 };
 
 // Words of BdcMatrix::rem_mask for n rows (one bit per 64 rows).
@@ -130,8 +133,9 @@ int exclusive_scan_i32(const int32_t *cnt, int32_t *out, int64_t N,
 // api.hip: handle creation shared with the autotuner
 mhdc_launch default_launch(int32_t n, int32_t n_b, int64_t nnz, double row_repeat,
                            int32_t far_offset);
-// Run length (tiles per XCD run, 8..16) that keeps the x rows a tile reads
-// through its farthest diagonals in the tile's own XCD (16 without a DIA part).
+// Run length (tiles per XCD run, runs of 2048..4096 rows: 8..16 tiles of
+// 256 rows) that keeps the x rows a tile reads through its farthest
+// diagonals in the tile's own XCD (the longest without a DIA part).
 int32_t xcd_run(int32_t far_offset, int32_t tile_rows);
 
 }  // namespace mhdc

@@ -56,6 +56,10 @@ KernelFn pick_v(int v, int kc, int parts)
             return pick_rem<WG, 2, 2>(parts);
         if (kc == 4)
             return pick_rem<WG, 2, 4>(parts);
+        if (kc == 8)
+            return pick_rem<WG, 2, 8>(parts);
+        if (kc == 16)
+            return pick_rem<WG, 2, 16>(parts);
         return nullptr;
     case 4: return kc == 1 ? pick_rem<WG, 4, 1>(parts) : nullptr;
     }
@@ -161,13 +165,26 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
     int rc = check_operands(m, X, ldx, Y, ldy, k);
     if (rc || m.n == 0)
         return rc;
-    int32_t v = m.launch.rows_per_lane, wg = m.launch.wg_size;
+    int32_t v = m.launch.rows_per_lane, wg = m.launch.wg_size, remap = m.launch.xcd_remap;
     const int group = m.launch.rhs_group > 0 ? m.launch.rhs_group : 16;
     const int kc = kc_for(k < group ? k : group);
-    // registers: 4 rows per lane only for one right-hand side, 2 up to four
-    if (kc >= 8)
-        v = 1;
-    else if (kc > 1 && v > 2)
+    // Several right-hand sides on a handle with a DIA part and no CSR part,
+    // still in its default launch of 256-lane tiles: two adjacent rows per
+    // lane (16-byte x and y accesses per column; 1.24x at 16 columns on the
+    // 256^3 stencil), XCD runs chosen for the 512-row tiles.  Next to a CSR
+    // part the pairs lose (the lanes' remainder gathers no longer fall on
+    // neighbouring rows: 1.14x slower at 16 columns on the partially
+    // diagonal 192^3 matrix).
+    const mhdc_launch &L = m.launch, &D = m.dflt;
+    const bool is_default = L.rows_per_lane == D.rows_per_lane && L.wg_size == D.wg_size &&
+                            L.xcd_remap == D.xcd_remap && L.csr_mode == D.csr_mode &&
+                            L.rhs_group == D.rhs_group;
+    if (kc > 1 && wg == 256 && m.K > 0 && m.R == 0 && is_default && remap >= 2) {
+        v = 2;
+        remap = xcd_run(m.far_offset, 2 * wg);
+    }
+    // registers: 4 rows per lane only for one right-hand side
+    if (kc > 1 && v > 2)
         v = 2;
     const bool has_dia = m.K > 0;
     const bool has_rem = m.R > 0;
@@ -183,6 +200,7 @@ int launch_spmv(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, v);
+        a.remap = remap;
         const int64_t T = (int64_t)wg * v;
         const int64_t tiles = ((int64_t)m.n + T - 1) / T;
         if (tiles > INT32_MAX)

@@ -139,14 +139,25 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
     using Shape = TileShape<WG, KC, RG>;
     constexpr int T = WG * V;
     constexpr int CH = Shape::CH;
-    // eight diagonals in flight for pure DIA tiles, four next to a CSR part
-    constexpr int U = (KC == 1 && HAS_REM) ? 4 : (KC >= 8 ? U8 : Shape::U);
+    // Several right-hand sides at two rows per lane: the lane's rows are
+    // adjacent, so each column's x pair and y pair move as one 16-byte
+    // access (half the load instructions per diagonal); otherwise the rows
+    // of a lane lie one wavefront apart.  The arithmetic per row is the same.
+    constexpr bool ADJ = KC >= 2 && V == 2;
+    typedef double pair8 __attribute__((ext_vector_type(2), aligned(8)));
+    // eight diagonals in flight for pure DIA tiles, four next to a CSR part;
+    // one at 8 and 16 columns with adjacent rows (registers)
+    constexpr int U = (KC == 1 && HAS_REM) ? 4 : (KC >= 8 ? (ADJ ? 1 : U8) : Shape::U);
     constexpr int UR = Shape::UR;
     const int n = a.n;
     const int64_t tile_base = tile * T;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wave_base = tile_base + (int64_t)wave * 64 * V;
+    // row of the lane's slot v
+    auto row_of = [&](int v) -> int64_t {
+        return ADJ ? wave_base + 2 * lane + v : wave_base + v * 64 + lane;
+    };
 
     double acc[V][KC];
 #pragma unroll
@@ -186,7 +197,7 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
             int32_t rs[V], re[V];
 #pragma unroll
             for (int v = 0; v < V; v++) {
-                const int64_t row = wave_base + v * 64 + lane;
+                const int64_t row = row_of(v);
                 rs[v] = row < n ? a.rem_ptr[row] : 0;
                 re[v] = row < n ? a.rem_ptr[row + 1] : 0;
             }
@@ -283,6 +294,48 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const double *seg = a.dia_val + (int64_t)(kk + u) * a.n_b + t0;
+                    if constexpr (ADJ) {
+                        // rows row0 and row0 + 1: 16-byte loads where both are in range
+                        const int64_t row0 = wave_base + 2 * lane;
+                        const int64_t j0 = row0 + off[u];
+                        in[u][0] = live[u] && row0 < n && j0 >= 0 && j0 < n;
+                        in[u][V - 1] = live[u] && row0 + 1 < n && j0 + 1 >= 0 && j0 + 1 < n;
+                        w[u][0] = 0.0;
+                        w[u][V - 1] = 0.0;
+#pragma unroll
+                        for (int r = 0; r < KC; r++) {
+                            xv[u][0][r] = 0.0;
+                            xv[u][V - 1][r] = 0.0;
+                        }
+                        if (in[u][0] && in[u][V - 1]) {
+                            const pair8 wv = __builtin_nontemporal_load(reinterpret_cast<const pair8 *>(seg + 2 * lane));
+                            w[u][0] = wv.x;
+                            w[u][V - 1] = wv.y;
+#pragma unroll
+                            for (int r = 0; r < KC; r++)
+                                if (r < kc_n) {
+                                    const pair8 xx = *reinterpret_cast<const pair8 *>(Xg + r * a.ldx + j0);
+                                    xv[u][0][r] = xx.x;
+                                    xv[u][V - 1][r] = xx.y;
+                                }
+                        } else {
+                            if (in[u][0]) {
+                                w[u][0] = __builtin_nontemporal_load(seg + 2 * lane);
+#pragma unroll
+                                for (int r = 0; r < KC; r++)
+                                    if (r < kc_n)
+                                        xv[u][0][r] = Xg[r * a.ldx + j0];
+                            }
+                            if (in[u][V - 1]) {
+                                w[u][V - 1] = __builtin_nontemporal_load(seg + 2 * lane + 1);
+#pragma unroll
+                                for (int r = 0; r < KC; r++)
+                                    if (r < kc_n)
+                                        xv[u][V - 1][r] = Xg[r * a.ldx + j0 + 1];
+                            }
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int v = 0; v < V; v++) {
                         const int64_t row = wave_base + v * 64 + lane;
@@ -316,7 +369,7 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
             // own block's list, two diagonals at a time.
 #pragma unroll
             for (int v = 0; v < V; v++) {
-                const int64_t row = wave_base + v * 64 + lane;
+                const int64_t row = row_of(v);
                 if (row < n) {
                     const int64_t ib = row / a.n_b;
                     const int64_t t = row - ib * a.n_b;
@@ -368,6 +421,22 @@ __device__ inline void spmv_tile_cols(const SpmvArgs &a, int64_t tile, void *lds
         }
     }
 
+    if constexpr (ADJ) {
+        const int64_t row0 = wave_base + 2 * lane;
+#pragma unroll
+        for (int r = 0; r < KC; r++)
+            if (r < kc_n) {
+                if (row0 + 1 < n) {
+                    pair8 yv;
+                    yv.x = acc[0][r];
+                    yv.y = acc[V - 1][r];
+                    __builtin_nontemporal_store(yv, reinterpret_cast<pair8 *>(Yg + r * a.ldy + row0));
+                } else if (row0 < n) {
+                    __builtin_nontemporal_store(acc[0][r], Yg + r * a.ldy + row0);
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int v = 0; v < V; v++) {
         const int64_t row = wave_base + v * 64 + lane;
