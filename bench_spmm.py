@@ -1,15 +1,18 @@
 """Multi-right-hand-side products Y = A X (k = 1, 2, 4, 8, 16) on the
 heptadiagonal 7-point 256^3 matrix (M-HDC n_b = 256, theta = 0.6, and CSR)
 and on the partially diagonal 27-point 192^3 matrix (M-HDC n_b = 128, CSR).
-X and Y are column-major (n x k, leading dimension n) or, with --layouts
-rowmajor, stored row by row (element (i, r) at X[i*k + r]); A is read once
-per launch, so algorithmic bytes = A + 16 n k.  Each handle runs its default
+X and Y are column-major (n x k, leading dimension n): `colmajor` runs the
+column-major kernel (spmm), `colmajor_ws` the workspace entry (spmm_ws,
+route 0: the library's choice, printed as route 1 = column-major kernel or
+2 = transposed through the row-major kernel); `rowmajor` stores them row
+by row (element (i, r) at X[i*k + r]).  A is read once per product, so
+algorithmic bytes = A + 16 n k (the transpositions of route 2 are extra).  Each handle runs its default
 launch shape; a step is one spmm with inputs resident in HBM, timed with
 HIP events on the launch stream.
 
     python bench_spmm.py [--steps K] [--warmup W] [--matrix all|hepta|partial]
                          [--ks 1,2,4,8,16] [--formats mhdc,csr]
-                         [--layouts colmajor,rowmajor]
+                         [--layouts colmajor,colmajor_ws,rowmajor]
 
 Prints one JSON line; value = GFLOP/s of M-HDC at k = 16 on the 256^3 case.
 """
@@ -49,8 +52,8 @@ def main():
     ap.add_argument("--matrix", choices=("all", "hepta", "partial"), default="all")
     ap.add_argument("--ks", default="1,2,4,8,16", help="right-hand side counts, comma-separated")
     ap.add_argument("--formats", default="mhdc,csr", help="subset of mhdc,csr")
-    ap.add_argument("--layouts", default="colmajor,rowmajor",
-                    help="subset of colmajor,rowmajor")
+    ap.add_argument("--layouts", default="colmajor,colmajor_ws,rowmajor",
+                    help="subset of colmajor,colmajor_ws,rowmajor")
     args = ap.parse_args()
     ks = [int(t) for t in args.ks.split(",")]
     formats = args.formats.split(",")
@@ -82,9 +85,15 @@ def main():
             a_bytes = inf["bytes_alg"] - 16.0 * n
             for k in ks:
                 for lay in layouts:
+                    route = None
                     if lay == "rowmajor":
                         X = torch.rand((n, k), dtype=torch.float64, device=dev)
                         fn = lambda: h.spmm_rowmajor(X, Y, s)  # noqa: E731
+                    elif lay == "colmajor_ws":
+                        X = torch.rand((k, n), dtype=torch.float64, device=dev)
+                        ws = torch.empty(h.workspace_bytes(k), dtype=torch.uint8, device=dev)
+                        route = h.ws_route(k)
+                        fn = lambda: h.spmm_ws(X, Y, 0, ws, s)  # noqa: E731
                     else:
                         X = torch.rand((k, n), dtype=torch.float64, device=dev)
                         fn = lambda: h.spmm(X, Y, s)  # noqa: E731
@@ -92,11 +101,15 @@ def main():
                     t = timed(fn, args.steps, args.warmup, s)
                     gbs = (a_bytes + 16.0 * n * k) / t / 1e9
                     gfl = 2.0 * m.nnz * k / t / 1e9
-                    log("%-34s %-12s %-8s k=%2d %9.1f us %7.1f GB/s %7.1f GFLOP/s" % (
-                        name, label, lay, k, t * 1e6, gbs, gfl))
+                    log("%-34s %-12s %-11s k=%2d %9.1f us %7.1f GB/s %7.1f GFLOP/s%s" % (
+                        name, label, lay, k, t * 1e6, gbs, gfl,
+                        "" if route is None else "  route %d" % route))
                     rows.append(dict(matrix=name, format=label, layout=lay, k=k,
                                      us=round(t * 1e6, 2), gb_per_s=round(gbs, 1),
                                      gflops=round(gfl, 1), bytes_alg=a_bytes + 16.0 * n * k))
+                    if route is not None:
+                        rows[-1]["route"] = route
+                        del ws
                     del X, Y
             h.close()
         del d, m

@@ -41,6 +41,7 @@
 #ifndef MHDC_H
 #define MHDC_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -102,6 +103,10 @@ typedef struct {
     double row_repeat;   /* share of the CSR part's nonempty rows whose column
                             offsets (col - row) repeat the previous row's, in
                             length and order; 0 for an empty CSR part */
+    double lone_per_row; /* CSR-part entries per row (over all n rows) with no
+                            column within 16 of theirs in the CSR part of
+                            either of the two previous rows (rows before the
+                            first hold none); 0 for an empty CSR part */
 } mhdc_info;
 
 /* Launch shape of the SpMV kernel.  rows_per_lane in {1, 2, 4} (4 only for
@@ -175,6 +180,35 @@ int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
 int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y,
                        int64_t ldy, int32_t k, hipStream_t stream);
 
+/* Y = A X for column-major X and Y exactly as mhdc_spmm (same arguments,
+ * same checks, same bits), given a workspace that lets it take the
+ * row-major kernel: route 2 transposes X into the workspace (a row-major
+ * copy, element (i, r) at ws[i*k' + r], k' = k rounded up to even; 256 rows
+ * per workgroup through LDS), then runs the kernel of mhdc_spmm_rowmajor on
+ * the copy, storing Y by column; route 1 is mhdc_spmm (ws unused); route 0
+ * takes the route mhdc_spmm_ws_route names.  The detour moves 2*n*k'
+ * doubles more and pays where the CSR part gathers scattered columns: each
+ * such gather then reads one row of X instead of one cache line per
+ * column.
+ * ws: device memory of at least mhdc_spmm_workspace_bytes(h, k) bytes,
+ * 256-byte aligned, overlapping neither X nor Y (INVALID_ARG otherwise,
+ * when route 2 is taken); owned by the caller, who keeps it alive until
+ * the work queued on the stream has finished; calls that share one
+ * workspace must not overlap in time (different streams race).  Allocates
+ * nothing.  Asynchronous: two launches on route 2. */
+int mhdc_spmm_ws(mhdc_handle h, const double *X, int64_t ldx, double *Y,
+                 int64_t ldy, int32_t k, int32_t route, void *ws,
+                 size_t ws_bytes, hipStream_t stream);
+/* Workspace bytes of mhdc_spmm_ws for k right-hand sides (1..16):
+ * 8*n*k', the row-major copy of X. */
+int mhdc_spmm_workspace_bytes(mhdc_handle h, int32_t k, size_t *bytes);
+/* The route mhdc_spmm_ws takes for route 0 and k right-hand sides:
+ * 2 when k >= 4 and k * lone_per_row (mhdc_info) >= 4, else 1.  A lone
+ * entry's gather from column-major X touches one cache line per column
+ * that no neighbouring row shares; the row-major copy serves all k
+ * columns from one line. */
+int mhdc_spmm_ws_route(mhdc_handle h, int32_t k, int32_t *route);
+
 /* Decode back to CSR on the device: rowptr[n+1], colind[nnz], val[nnz]
  * (nnz from mhdc_get_info).  Row i merges, by column, its remainder entries
  * and the nonzero slots of its block's partial diagonals; for canonical CSR
@@ -214,6 +248,12 @@ int hdc_spmm(hdc_handle h, const double *X, int64_t ldx, double *Y,
 /* Row-major right-hand sides as in mhdc_spmm_rowmajor. */
 int hdc_spmm_rowmajor(hdc_handle h, const double *X, int64_t ldx, double *Y,
                       int64_t ldy, int32_t k, hipStream_t stream);
+/* Column-major right-hand sides through a workspace as in mhdc_spmm_ws. */
+int hdc_spmm_ws(hdc_handle h, const double *X, int64_t ldx, double *Y,
+                int64_t ldy, int32_t k, int32_t route, void *ws,
+                size_t ws_bytes, hipStream_t stream);
+int hdc_spmm_workspace_bytes(hdc_handle h, int32_t k, size_t *bytes);
+int hdc_spmm_ws_route(hdc_handle h, int32_t k, int32_t *route);
 int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val,
                int32_t *rem_ptr, int32_t *rem_col, double *rem_val);
 int hdc_get_info(hdc_handle h, mhdc_info *out);
@@ -231,6 +271,12 @@ int csr_spmm(csr_handle h, const double *X, int64_t ldx, double *Y,
 /* Row-major right-hand sides as in mhdc_spmm_rowmajor. */
 int csr_spmm_rowmajor(csr_handle h, const double *X, int64_t ldx, double *Y,
                       int64_t ldy, int32_t k, hipStream_t stream);
+/* Column-major right-hand sides through a workspace as in mhdc_spmm_ws. */
+int csr_spmm_ws(csr_handle h, const double *X, int64_t ldx, double *Y,
+                int64_t ldy, int32_t k, int32_t route, void *ws,
+                size_t ws_bytes, hipStream_t stream);
+int csr_spmm_workspace_bytes(csr_handle h, int32_t k, size_t *bytes);
+int csr_spmm_ws_route(csr_handle h, int32_t k, int32_t *route);
 int csr_get_info(csr_handle h, mhdc_info *out);
 int csr_set_launch(csr_handle h, const mhdc_launch *cfg);
 void csr_destroy(csr_handle h);

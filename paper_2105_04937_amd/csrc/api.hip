@@ -113,6 +113,7 @@ void fill_info(const BdcMatrix &m, mhdc_info *o)
     o->csr_mode = m.launch.csr_mode;
     o->rhs_group = m.launch.rhs_group;
     o->row_repeat = m.row_repeat;
+    o->lone_per_row = m.lone_per_row;
 }
 
 int check_theta_nb(int32_t n, int32_t n_b, double theta, bool need_nb)
@@ -287,6 +288,37 @@ int mhdc_spmm_rowmajor(mhdc_handle h, const double *X, int64_t ldx, double *Y, i
     return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
 }
 
+int mhdc_spmm_ws(mhdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t k,
+                int32_t route, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_ws(h->m, X, ldx, Y, ldy, k, route, ws, ws_bytes, stream);
+}
+
+int mhdc_spmm_workspace_bytes(mhdc_handle h, int32_t k, size_t *bytes)
+{
+    clear_error();
+    if (!h || !bytes)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or bytes is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *bytes = spmm_ws_bytes(h->m, k);
+    return MHDC_OK;
+}
+
+int mhdc_spmm_ws_route(mhdc_handle h, int32_t k, int32_t *route)
+{
+    clear_error();
+    if (!h || !route)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or route is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *route = spmm_ws_prefers_rm(h->m, k) ? 2 : 1;
+    return MHDC_OK;
+}
+
 int mhdc_to_csr(mhdc_handle h, int32_t *rowptr, int32_t *colind, double *val)
 {
     clear_error();
@@ -380,6 +412,37 @@ int hdc_spmm_rowmajor(hdc_handle h, const double *X, int64_t ldx, double *Y, int
     return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
 }
 
+int hdc_spmm_ws(hdc_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t k,
+               int32_t route, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_ws(h->m, X, ldx, Y, ldy, k, route, ws, ws_bytes, stream);
+}
+
+int hdc_spmm_workspace_bytes(hdc_handle h, int32_t k, size_t *bytes)
+{
+    clear_error();
+    if (!h || !bytes)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or bytes is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *bytes = spmm_ws_bytes(h->m, k);
+    return MHDC_OK;
+}
+
+int hdc_spmm_ws_route(hdc_handle h, int32_t k, int32_t *route)
+{
+    clear_error();
+    if (!h || !route)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or route is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *route = spmm_ws_prefers_rm(h->m, k) ? 2 : 1;
+    return MHDC_OK;
+}
+
 int hdc_export(hdc_handle h, int32_t *dia_off, double *dia_val, int32_t *rem_ptr,
                int32_t *rem_col, double *rem_val)
 {
@@ -461,6 +524,37 @@ int csr_spmm_rowmajor(csr_handle h, const double *X, int64_t ldx, double *Y, int
     if (!h)
         return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
     return launch_spmm_rm(h->m, X, ldx, Y, ldy, k, stream);
+}
+
+int csr_spmm_ws(csr_handle h, const double *X, int64_t ldx, double *Y, int64_t ldy, int32_t k,
+               int32_t route, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    if (!h)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle is NULL");
+    return launch_spmm_ws(h->m, X, ldx, Y, ldy, k, route, ws, ws_bytes, stream);
+}
+
+int csr_spmm_workspace_bytes(csr_handle h, int32_t k, size_t *bytes)
+{
+    clear_error();
+    if (!h || !bytes)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or bytes is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *bytes = spmm_ws_bytes(h->m, k);
+    return MHDC_OK;
+}
+
+int csr_spmm_ws_route(csr_handle h, int32_t k, int32_t *route)
+{
+    clear_error();
+    if (!h || !route)
+        return set_error(MHDC_ERR_INVALID_ARG, "handle or route is NULL");
+    if (k < 1 || k > 16)
+        return set_error(MHDC_ERR_INVALID_ARG, "k must be in [1, 16]");
+    *route = spmm_ws_prefers_rm(h->m, k) ? 2 : 1;
+    return MHDC_OK;
 }
 
 int csr_get_info(csr_handle h, mhdc_info *out)

@@ -299,22 +299,53 @@ __global__ __launch_bounds__(CV_WG) void k_max_abs_offset(int64_t K, const int32
         atomicMax(out, m);
 }
 
+// Whether the ascending columns col[b, e) hold one within LONE_REACH of j
+// (binary search for the first column >= j - LONE_REACH).
+constexpr int32_t LONE_REACH = 16;
+__device__ inline bool has_near(const int32_t *__restrict__ col, int32_t b, int32_t e, int32_t j)
+{
+    const int64_t lo_col = (int64_t)j - LONE_REACH;
+    int32_t lo = b, hi = e;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)col[mid] < lo_col)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < e && (int64_t)col[lo] <= (int64_t)j + LONE_REACH;
+}
+
 // One lane per row of a CSR-shaped pair (ptr, col): cnt[0] counts the rows
 // with entries, cnt[1] those of them whose column offsets col - row repeat
-// the previous row's (same length, same offsets in order).  Where most rows
-// repeat (stencils), the lanes of a wavefront gathering x for their own rows
-// read neighbouring elements.
+// the previous row's (same length, same offsets in order), cnt[2] the lone
+// entries: those with no column within LONE_REACH (16 doubles, one 128-byte
+// line) in either of the two previous rows.  Where most rows repeat
+// (stencils), the lanes of a wavefront gathering x for their own rows read
+// neighbouring elements; a lone entry's gather shares no cache line with
+// its neighbours' rows, one line per right-hand side stored by column.
 __global__ __launch_bounds__(CV_WG) void k_row_repeat(int32_t n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       unsigned long long *cnt)
 {
     uint32_t ne = 0, rep = 0;
+    unsigned long long lone = 0;
     for (int64_t i = (int64_t)blockIdx.x * CV_WG + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * CV_WG) {
         const int32_t b1 = ptr[i], e1 = ptr[i + 1];
         if (e1 == b1)
             continue;
         ne++;
+        {
+            const int32_t bm2 = i >= 2 ? ptr[i - 2] : 0, bm1 = i >= 1 ? ptr[i - 1] : 0;
+            for (int32_t e = b1; e < e1; e++) {
+                const int32_t j = col[e];
+                lone += (i < 1 || !has_near(col, bm1, b1, j)) &&
+                                (i < 2 || !has_near(col, bm2, bm1, j))
+                            ? 1u
+                            : 0u;
+            }
+        }
         if (i == 0)
             continue;
         const int32_t b0 = ptr[i - 1];
@@ -331,21 +362,25 @@ __global__ __launch_bounds__(CV_WG) void k_row_repeat(int32_t n, const int32_t *
     for (int sh = 32; sh >= 1; sh >>= 1) {
         ne += __shfl_xor(ne, sh, 64);
         rep += __shfl_xor(rep, sh, 64);
+        lone += __shfl_xor(lone, sh, 64);
     }
-    __shared__ unsigned long long s_sum[2][CV_WG / 64];
+    __shared__ unsigned long long s_sum[3][CV_WG / 64];
     if ((threadIdx.x & 63) == 0) {
         s_sum[0][threadIdx.x >> 6] = ne;
         s_sum[1][threadIdx.x >> 6] = rep;
+        s_sum[2][threadIdx.x >> 6] = lone;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
+        unsigned long long a = 0, b = 0, c = 0;
         for (int w = 0; w < CV_WG / 64; w++) {
             a += s_sum[0][w];
             b += s_sum[1][w];
+            c += s_sum[2][w];
         }
         atomicAdd(cnt, a);
         atomicAdd(cnt + 1, b);
+        atomicAdd(cnt + 2, c);
     }
 }
 
@@ -509,25 +544,29 @@ int max_abs_offset(int64_t K, const int32_t *off, int32_t *far)
 }
 
 // Share of the CSR part's nonempty rows that repeat the previous row's
-// column offsets (k_row_repeat); 0 for an empty CSR part.
-int row_repeat_share(int32_t n, const int32_t *ptr, const int32_t *col, double *share)
+// column offsets, and its lone entries per row (k_row_repeat); both 0 for
+// an empty CSR part.
+int row_repeat_share(int32_t n, const int32_t *ptr, const int32_t *col, double *share,
+                     double *lone_per_row)
 {
     *share = 0.0;
-    if (n <= 1)
+    *lone_per_row = 0.0;
+    if (n < 1)
         return MHDC_OK;
     unsigned long long *cnt = nullptr;
-    int rc = dmalloc((void **)&cnt, 2 * sizeof(unsigned long long), "row repeat counts");
+    int rc = dmalloc((void **)&cnt, 3 * sizeof(unsigned long long), "row repeat counts");
     if (rc)
         return rc;
     TempSet tmp;
     tmp.add(cnt);
-    MHDC_HIP_CHECK(hipMemset(cnt, 0, 2 * sizeof(unsigned long long)));
+    MHDC_HIP_CHECK(hipMemset(cnt, 0, 3 * sizeof(unsigned long long)));
     k_row_repeat<<<grid_for(n, CV_WG, 1 << 12), CV_WG, 0, 0>>>(n, ptr, col, cnt);
     if ((rc = launch_ok("row repeat")))
         return rc;
-    unsigned long long h[2] = {0, 0};
+    unsigned long long h[3] = {0, 0, 0};
     MHDC_HIP_CHECK(hipMemcpy(h, cnt, sizeof(h), hipMemcpyDeviceToHost));
     *share = h[0] > 0 ? (double)h[1] / (double)h[0] : 0.0;
+    *lone_per_row = (double)h[2] / (double)n;
     return MHDC_OK;
 }
 
@@ -748,7 +787,7 @@ int build_blocked(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, co
             dfree(m.rem_mask);
             m.rem_mask = nullptr;
         }
-        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat)))
+        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat, &m.lone_per_row)))
             return rc;
     }
     return sync_ok("conversion");
@@ -779,7 +818,7 @@ int build_csr(BdcMatrix &m, const int32_t *rowptr, const int32_t *colind, const 
                                  hipMemcpyDeviceToDevice));
         MHDC_HIP_CHECK(hipMemcpy(m.rem_val, val, sizeof(double) * (size_t)nnz,
                                  hipMemcpyDeviceToDevice));
-        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat)))
+        if ((rc = row_repeat_share(n, m.rem_ptr, m.rem_col, &m.row_repeat, &m.lone_per_row)))
             return rc;
     }
     return sync_ok("csr copy");

@@ -37,6 +37,11 @@ struct BdcMatrix {
     // Share of the CSR part's nonempty rows whose column offsets repeat the
     // previous row's (0 when the CSR part is empty); picks the CSR mode.
     double row_repeat = 0.0;
+    // CSR-part entries per row with no column within 16 of theirs in the
+    // two previous rows (0 when the CSR part is empty): gathers that share
+    // no cache line with the neighbouring rows'; picks the route of
+    // column-major products given a workspace.
+    double lone_per_row = 0.0;
     // Largest |offset| of the DIA part's diagonals (0 without a DIA part):
     // how far a tile's x rows lie from its own rows; picks the XCD run length.
     int32_t far_offset = 0;
@@ -124,6 +129,13 @@ int rm_columns(int32_t k);  // accumulator width of the row-major kernel (2..16)
 bool rm_row_gather(const BdcMatrix &m);
 int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
                    int32_t k, hipStream_t stream);
+// Column-major right-hand sides with a caller workspace: route 1 = the
+// column-major kernel, 2 = transposed into the workspace, the row-major
+// kernel, transposed back (same bits), 0 = 2 where spmm_ws_prefers_rm.
+size_t spmm_ws_bytes(const BdcMatrix &m, int32_t k);
+bool spmm_ws_prefers_rm(const BdcMatrix &m, int32_t k);
+int launch_spmm_ws(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                   int32_t k, int32_t route, void *ws, size_t ws_bytes, hipStream_t stream);
 
 // scan.hip: exclusive prefix sum of cnt[0..N) into out[0..N] (out[N] =
 // total), all int32 on the device; total also returned on the host.

@@ -68,6 +68,59 @@ __global__ __launch_bounds__(256) void k_zero_rows(double *Y, int64_t ldy, int32
     }
 }
 
+// Transposition of column-major right-hand sides (column r at X + r*ldx)
+// into a row-major copy W (element (i, r) at W[i*ld + r], ld = k rounded up
+// to even, so rows start 16-byte aligned).  One workgroup moves TR_ROWS
+// rows through LDS so that both sides are read and written in contiguous
+// runs: a column's TR_ROWS doubles in, the rows' TR_ROWS*ld doubles out as
+// 16-byte pairs.  The pad column of an odd k is written as zero and never
+// read as data.
+constexpr int TR_ROWS = 256;
+constexpr int TR_PAD = TR_ROWS + 1;  // LDS row stride of one column
+
+template <int KC>
+__global__ __launch_bounds__(TR_ROWS) void k_cols_to_rows(const double *__restrict__ X,
+                                                          int64_t ldx, double *__restrict__ W,
+                                                          int32_t ld, int32_t n, int32_t k)
+{
+    __shared__ double t[KC * TR_PAD];
+    const int64_t r0 = (int64_t)blockIdx.x * TR_ROWS;
+    const int rows = (int)min((int64_t)TR_ROWS, (int64_t)n - r0);
+    const int tid = threadIdx.x;
+    if (tid < rows) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c < k)
+                t[c * TR_PAD + tid] = __builtin_nontemporal_load(X + c * ldx + r0 + tid);
+    }
+    __syncthreads();
+    const int half = ld / 2;
+    rm_pair *w = reinterpret_cast<rm_pair *>(W + r0 * ld);
+    for (int e = tid; e < rows * half; e += TR_ROWS) {
+        const int row = e / half, c = 2 * (e - row * half);
+        rm_pair v;
+        v.x = t[c * TR_PAD + row];
+        v.y = c + 1 < k ? t[(c + 1) * TR_PAD + row] : 0.0;
+        w[e] = v;
+    }
+}
+
+using TransposeFn = void (*)(const double *, int64_t, double *, int32_t, int32_t, int32_t);
+
+TransposeFn pick_cols_to_rows(int kc)
+{
+    switch (kc) {
+    case 2: return k_cols_to_rows<2>;
+    case 4: return k_cols_to_rows<4>;
+    case 8: return k_cols_to_rows<8>;
+    case 16: return k_cols_to_rows<16>;
+    }
+    return nullptr;
+}
+
+// Row stride of the row-major copy of X.
+int32_t ws_ld(int32_t k) { return (k + 1) & ~1; }
+
 }  // namespace
 
 int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const double *Y,
@@ -107,16 +160,14 @@ int rm_columns(int32_t k)
     return kc < 2 ? 2 : kc;
 }
 
-int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
-                   int32_t k, hipStream_t stream)
+namespace {
+
+// The row-major kernel on checked operands; y_cols: Y by column (ldy >= n)
+// instead of by row.  A matrix without entries takes the zero fill, which
+// writes Y by row: callers with y_cols handle it themselves.
+int launch_rm_kernel(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                     int32_t k, bool y_cols, hipStream_t stream)
 {
-    int rc = check_operands_rm(m, X, ldx, Y, ldy, k);
-    if (rc || m.n == 0)
-        return rc;
-    // one right-hand side with unit strides is a plain vector: the
-    // single-column kernel, same bits
-    if (k == 1 && ldx == 1 && ldy == 1)
-        return launch_spmv(m, X, m.n, Y, m.n, 1, stream);
     const int32_t wg = m.launch.wg_size;
     const bool has_dia = m.K > 0;
     const bool has_rem = m.R > 0;
@@ -130,7 +181,8 @@ int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, 1);
-        a.pairs = rm_pairs(X, ldx, Y, ldy);
+        a.pairs = rm_pairs(X, ldx, y_cols ? X : Y, y_cols ? ldx : ldy);
+        a.y_cols = y_cols ? 1 : 0;
         const int64_t tiles = ((int64_t)m.n + wg - 1) / wg;
         if (tiles > INT32_MAX)
             return set_error(MHDC_ERR_SIZE, "too many tiles");
@@ -140,6 +192,73 @@ int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
     if (e != hipSuccess)
         return set_error(MHDC_ERR_HIP, std::string("row-major spmm launch: ") + hipGetErrorString(e));
     return MHDC_OK;
+}
+
+}  // namespace
+
+int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                   int32_t k, hipStream_t stream)
+{
+    int rc = check_operands_rm(m, X, ldx, Y, ldy, k);
+    if (rc || m.n == 0)
+        return rc;
+    // one right-hand side with unit strides is a plain vector: the
+    // single-column kernel, same bits
+    if (k == 1 && ldx == 1 && ldy == 1)
+        return launch_spmv(m, X, m.n, Y, m.n, 1, stream);
+    return launch_rm_kernel(m, X, ldx, Y, ldy, k, false, stream);
+}
+
+size_t spmm_ws_bytes(const BdcMatrix &m, int32_t k)
+{
+    return (size_t)m.n * ws_ld(k) * 8;
+}
+
+// Lone gathers cost one cache line per column from column-major X and about
+// one line per row from the row-major copy (k <= 16 doubles), against 4k
+// extra doubles per row of transposition.  Measured on MI355X, the route
+// through the row-major kernel gained 1.1-2.1x from 1 to 2 lone entries
+// per row at k = 4..16 (random columns) and lost 5-45 % on stencil
+// matrices whose CSR part has none.
+bool spmm_ws_prefers_rm(const BdcMatrix &m, int32_t k)
+{
+    return k >= 4 && m.R > 0 && m.lone_per_row * k >= 4.0;
+}
+
+int launch_spmm_ws(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                   int32_t k, int32_t route, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    int rc = check_operands(m, X, ldx, Y, ldy, k);
+    if (rc)
+        return rc;
+    if (route < 0 || route > 2)
+        return set_error(MHDC_ERR_INVALID_ARG, "route must be 0, 1 or 2");
+    const bool via_rm = route == 2 || (route == 0 && spmm_ws_prefers_rm(m, k));
+    // a matrix without entries only zeroes Y: no detour
+    if (!via_rm || m.n == 0 || (m.K == 0 && m.R == 0))
+        return launch_spmv(m, X, ldx, Y, ldy, k, stream);
+    const size_t need = spmm_ws_bytes(m, k);
+    if (!ws || ws_bytes < need)
+        return set_error(MHDC_ERR_INVALID_ARG,
+                         "workspace smaller than mhdc_spmm_workspace_bytes (" +
+                             std::to_string(need) + " bytes)");
+    if (((uintptr_t)ws & 255) != 0)
+        return set_error(MHDC_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    const char *wb = (const char *)ws, *we = wb + need;
+    const char *xb = (const char *)X, *xe = (const char *)(X + (int64_t)(k - 1) * ldx + m.n);
+    const char *yb = (const char *)Y, *ye = (const char *)(Y + (int64_t)(k - 1) * ldy + m.n);
+    if ((wb < xe && xb < we) || (wb < ye && yb < we))
+        return set_error(MHDC_ERR_INVALID_ARG, "workspace overlaps X or Y");
+    const int32_t ld = ws_ld(k);
+    double *Xr = (double *)ws;
+    const unsigned blocks = (unsigned)(((int64_t)m.n + TR_ROWS - 1) / TR_ROWS);
+    hipLaunchKernelGGL(pick_cols_to_rows(rm_columns(k)), dim3(blocks), dim3(TR_ROWS), 0, stream,
+                       X, ldx, Xr, ld, m.n, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(MHDC_ERR_HIP, std::string("transpose launch: ") + hipGetErrorString(e));
+    // the row-major kernel on the copy, storing Y by column
+    return launch_rm_kernel(m, Xr, ld, Y, ldy, k, true, stream);
 }
 
 }  // namespace mhdc

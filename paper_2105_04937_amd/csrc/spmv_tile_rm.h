@@ -321,6 +321,44 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
         }
     }
 
+    if (a.y_cols) {
+        if constexpr (HAS_REM) {
+            // Y by column through LDS: the wavefront puts its 64 rows x KC
+            // columns in its own region (column stride 65 doubles), then
+            // stores each column's 64 rows as one contiguous 512-byte run.
+            // The CSR part's staging area is free: its last chunk ended on
+            // a barrier, and its row pointers are no longer read.
+            static_assert(Sh::LDS_BYTES >= WG / 64 * KC * 65 * 8, "Y staging fits");
+            __syncthreads();
+            double *s_y = static_cast<double *>(lds) + wave * (KC * 65);
+#pragma unroll
+            for (int q = 0; q < LC; q++)
+#pragma unroll
+                for (int p = 0; p < P; p++)
+                    if (p < nl)
+                        s_y[(c0 + p) * 65 + s + RPI * q] = acc[q][p];
+            __syncthreads();
+            const int64_t row = wave_base + lane;
+            if (row < n)
+                for (int c = 0; c < a.k; c++)
+                    __builtin_nontemporal_store(s_y[c * 65 + lane], a.Y + (int64_t)c * a.ldy + row);
+        } else {
+            // no LDS in this variant: the RPI row slots of one store write
+            // RPI consecutive rows of each of the wavefront's columns
+#pragma unroll
+            for (int q = 0; q < LC; q++) {
+                const int64_t row = wave_base + s + RPI * q;
+                if (row < n && l0) {
+#pragma unroll
+                    for (int p = 0; p < P; p++)
+                        if (p < nl)
+                            __builtin_nontemporal_store(acc[q][p],
+                                                        a.Y + (int64_t)(c0 + p) * a.ldy + row);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < LC; q++) {
         const int64_t row = wave_base + s + RPI * q;

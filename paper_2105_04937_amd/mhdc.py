@@ -36,7 +36,7 @@ class Info(ctypes.Structure):
                 ("rp_est", ctypes.c_double), ("rows_per_lane", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("csr_mode", ctypes.c_int32), ("rhs_group", ctypes.c_int32),
-                ("row_repeat", ctypes.c_double)]
+                ("row_repeat", ctypes.c_double), ("lone_per_row", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -96,6 +96,9 @@ SIGNATURES = {
     "mhdc_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mhdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "mhdc_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "mhdc_spmm_ws": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp]),
+    "mhdc_spmm_workspace_bytes": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "mhdc_spmm_ws_route": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "mhdc_to_csr": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "mhdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mhdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
@@ -106,6 +109,9 @@ SIGNATURES = {
     "hdc_spmv_unblocked": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "hdc_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "hdc_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "hdc_spmm_ws": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp]),
+    "hdc_spmm_workspace_bytes": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdc_spmm_ws_route": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "hdc_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "hdc_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "hdc_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
@@ -114,6 +120,9 @@ SIGNATURES = {
     "csr_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "csr_spmm": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
     "csr_spmm_rowmajor": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "csr_spmm_ws": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp]),
+    "csr_spmm_workspace_bytes": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "csr_spmm_ws_route": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "csr_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "csr_set_launch": (ctypes.c_int, [_vp, ctypes.POINTER(Launch)]),
     "csr_destroy": (None, [_vp]),
@@ -263,6 +272,41 @@ class _Matrix:
             raise ValueError("Y must have shape (%d, %d)" % (k, self.n))
         _check(self._fn("spmm")(self._h, _dptr(X, torch.float64, "X"), self.n,
                                 _dptr(Y, torch.float64, "Y"), self.n, k, _stream(stream)))
+        return Y
+
+    def workspace_bytes(self, k):
+        """Bytes of the workspace spmm_ws needs for k right-hand sides."""
+        out = ctypes.c_size_t(0)
+        _check(self._fn("spmm_workspace_bytes")(self._h, k, ctypes.byref(out)))
+        return out.value
+
+    def ws_route(self, k):
+        """The route spmm_ws takes by default for k right-hand sides: 1 =
+        the column-major kernel, 2 = through the row-major kernel."""
+        out = _i32(0)
+        _check(self._fn("spmm_ws_route")(self._h, k, ctypes.byref(out)))
+        return out.value
+
+    def spmm_ws(self, X, Y=None, route=0, ws=None, stream=None):
+        """spmm with a workspace (C-ABI *_spmm_ws): same shapes and bits as
+        spmm; route 0 = the library's choice, 1 = column-major kernel,
+        2 = transposed through the row-major kernel.  ws: a device tensor of
+        at least workspace_bytes(k) bytes (allocated here when None)."""
+        if X.dim() != 2 or X.shape[1] != self.n:
+            raise ValueError("X must have shape (k, n)")
+        k = X.shape[0]
+        if Y is None:
+            Y = torch.empty((k, self.n), dtype=torch.float64, device=X.device)
+        if tuple(Y.shape) != (k, self.n):
+            raise ValueError("Y must have shape (%d, %d)" % (k, self.n))
+        if ws is None:
+            ws = torch.empty(self.workspace_bytes(k), dtype=torch.uint8, device=X.device)
+        if not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("ws must be a contiguous device tensor")
+        _check(self._fn("spmm_ws")(self._h, _dptr(X, torch.float64, "X"), self.n,
+                                   _dptr(Y, torch.float64, "Y"), self.n, k, route,
+                                   ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel() * ws.element_size(), _stream(stream)))
         return Y
 
     def spmm_rowmajor(self, X, Y=None, stream=None):
