@@ -79,7 +79,7 @@ def _lone_per_row(ptr, col):
 
 def test_lone_count_and_route_rule():
     """lone_per_row of the CSR part equals the host brute force exactly;
-    the default route is 2 exactly when k >= 4 and k * lone_per_row >= 4."""
+    the default route is 2 exactly when k >= 2 and k * lone_per_row >= 4."""
     cases = [("7-point 12^3", synth.heptadiagonal(12, 1)),
              ("27-point 10^3 octant drops", synth.partially_diagonal(10, 2)),
              ("27-point 10^3 one random column", synth.partially_diagonal(
@@ -100,7 +100,7 @@ def test_lone_count_and_route_rule():
                 want = _lone_per_row(t["rem_ptr"].cpu().numpy(), t["rem_col"].cpu().numpy())
             assert inf["lone_per_row"] == want, (name, kind, inf["lone_per_row"], want)
             for k in range(1, 17):
-                route = 2 if (k >= 4 and inf["R"] > 0 and want * k >= 4.0) else 1
+                route = 2 if (k >= 2 and inf["R"] > 0 and want * k >= 4.0) else 1
                 assert h.ws_route(k) == route, (name, kind, k)
                 seen.add(route)
             h.close()
@@ -179,6 +179,39 @@ def test_spmm_ws_empty_and_tiny():
         Y = h.spmm_ws(X, route=2)
         assert torch.equal(Y, 3.0 * X)
         h.close()
+
+
+def test_spmm_ws_graph_replay():
+    """Route 2 captured in a graph (it allocates nothing and records no
+    memset): four replays on fresh inputs, with eager work and
+    synchronisations between them, each equal to the eager column-major
+    product bit for bit."""
+    m = synth.partially_diagonal(11, 4)
+    h = mhdc.MHDCMatrix.from_csr(*dev(m), 64, 0.6)
+    assert h.info()["R"] > 0
+    k = 8
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    X = torch.rand((k, m.n), dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    ws = torch.empty(h.workspace_bytes(k), dtype=torch.uint8, device="cuda")
+    h.spmm_ws(X, Y, route=2, ws=ws)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    say("case: spmm_ws graph capture")
+    with torch.cuda.graph(graph):
+        h.spmm_ws(X, Y, route=2, ws=ws)
+    for rep in range(4):
+        say("case: spmm_ws graph replay %d" % rep)
+        X.copy_(torch.rand((k, m.n), dtype=torch.float64, device="cuda", generator=g))
+        want = h.spmm(X)
+        Y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y.view(torch.int64), want.view(torch.int64)), rep
+    del graph
+    h.close()
 
 
 @pytest.mark.slow
