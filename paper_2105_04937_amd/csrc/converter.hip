@@ -299,21 +299,18 @@ __global__ __launch_bounds__(CV_WG) void k_max_abs_offset(int64_t K, const int32
         atomicMax(out, m);
 }
 
-// Whether the ascending columns col[b, e) hold one within LONE_REACH of j
-// (binary search for the first column >= j - LONE_REACH).
+// Columns within LONE_REACH (16 doubles, one 128-byte line) count as near.
 constexpr int32_t LONE_REACH = 16;
-__device__ inline bool has_near(const int32_t *__restrict__ col, int32_t b, int32_t e, int32_t j)
+
+// Advances p over the ascending columns col[p, e) below j - LONE_REACH and
+// reports whether the next one lies within LONE_REACH of j.  For ascending
+// j the pointer only moves forward: one merge pass over the row.
+__device__ inline bool near_merge(const int32_t *__restrict__ col, int32_t &p, int32_t e, int32_t j)
 {
     const int64_t lo_col = (int64_t)j - LONE_REACH;
-    int32_t lo = b, hi = e;
-    while (lo < hi) {
-        const int32_t mid = lo + (hi - lo) / 2;
-        if ((int64_t)col[mid] < lo_col)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo < e && (int64_t)col[lo] <= (int64_t)j + LONE_REACH;
+    while (p < e && (int64_t)col[p] < lo_col)
+        p++;
+    return p < e && (int64_t)col[p] <= (int64_t)j + LONE_REACH;
 }
 
 // One lane per row of a CSR-shaped pair (ptr, col): cnt[0] counts the rows
@@ -337,13 +334,14 @@ __global__ __launch_bounds__(CV_WG) void k_row_repeat(int32_t n, const int32_t *
             continue;
         ne++;
         {
-            const int32_t bm2 = i >= 2 ? ptr[i - 2] : 0, bm1 = i >= 1 ? ptr[i - 1] : 0;
+            // rows before the first hold no columns
+            const int32_t bm1 = i >= 1 ? ptr[i - 1] : b1, bm2 = i >= 2 ? ptr[i - 2] : bm1;
+            int32_t p1 = bm1, p2 = bm2;
             for (int32_t e = b1; e < e1; e++) {
                 const int32_t j = col[e];
-                lone += (i < 1 || !has_near(col, bm1, b1, j)) &&
-                                (i < 2 || !has_near(col, bm2, bm1, j))
-                            ? 1u
-                            : 0u;
+                const bool n1 = near_merge(col, p1, b1, j);
+                const bool n2 = near_merge(col, p2, bm1, j);
+                lone += n1 || n2 ? 0u : 1u;
             }
         }
         if (i == 0)

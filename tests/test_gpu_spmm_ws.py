@@ -181,6 +181,73 @@ def test_spmm_ws_empty_and_tiny():
         h.close()
 
 
+def _random_case(seed):
+    """One seeded case: a matrix of a random family and size, a format, k
+    and padded leading dimensions."""
+    rng = np.random.default_rng(seed)
+    fam = int(rng.integers(0, 3))
+    if fam == 0:
+        n = int(rng.integers(1, 1500))
+        m = synth.random_csr(n, seed, density=float(rng.uniform(0.001, 0.02)),
+                             bands=tuple(int(b) for b in rng.integers(-40, 40, size=3)))
+    elif fam == 1:
+        m = synth.partially_diagonal(int(rng.integers(3, 13)), seed,
+                                     drop=float(rng.uniform(0, 0.6)),
+                                     extra_per_row=int(rng.integers(0, 3)))
+    else:
+        m = synth.banded_stencil(int(rng.integers(1, 5000)), int(rng.choice([3, 5, 7])), seed)
+    fmt = ("M-HDC", "HDC", "CSR")[int(rng.integers(0, 3))]
+    n_b = int(rng.choice([1, 7, 32, 64, 256]))
+    theta = float(rng.choice([0.3, 0.6, 0.9]))
+    k = int(rng.integers(1, 17))
+    ldx = m.n + int(rng.integers(0, 40))
+    ldy = m.n + int(rng.integers(0, 40))
+    return m, fmt, n_b, theta, k, ldx, ldy
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_spmm_ws_random_shapes(seed):
+    """Seeded random matrices, formats, k and leading dimensions: routes
+    0, 1 and 2 equal mhdc_spmm bit for bit (the padding of Y untouched), and
+    the last column equals the oracle's sequential kernel."""
+    m, fmt, n_b, theta, k, ldx, ldy = _random_case(seed)
+    say("case: spmm_ws random seed %d: %s n=%d nnz=%d n_b=%d theta=%.1f k=%d ldx=%d ldy=%d" % (
+        seed, fmt, m.n, m.nnz, n_b, theta, k, ldx, ldy))
+    d = dev(m)
+    if fmt == "M-HDC":
+        h = mhdc.MHDCMatrix.from_csr(*d, n_b, theta)
+        want_last = lambda x: oracle.mhdc_spmv(  # noqa: E731
+            oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, n_b, theta), x)
+    elif fmt == "HDC":
+        h = mhdc.HDCMatrix.from_csr(*d, theta)
+        want_last = lambda x: oracle.hdc_spmv(  # noqa: E731
+            oracle.hdc_from_csr(m.rowptr, m.colind, m.val, theta), x)
+    else:
+        h = mhdc.CSRMatrix.from_csr(*d)
+        want_last = lambda x: oracle.csr_spmv(m.rowptr, m.colind, m.val, x, 0)  # noqa: E731
+    lib = mhdc.lib()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    Xb = torch.rand((k, ldx), dtype=torch.float64, device="cuda", generator=g) - 0.5
+    Xc = Xb[:, :m.n].contiguous()
+    ref = h.spmm(Xc)
+    ws = torch.empty(h.workspace_bytes(k) + 256, dtype=torch.uint8, device="cuda")
+    for route in (0, 1, 2):
+        Yb = torch.full((k, ldy), -3.0, dtype=torch.float64, device="cuda")
+        rc = lib.mhdc_spmm_ws if fmt == "M-HDC" else (
+            lib.hdc_spmm_ws if fmt == "HDC" else lib.csr_spmm_ws)
+        r = rc(h._h, ctypes.c_void_p(Xb.data_ptr()), ldx, ctypes.c_void_p(Yb.data_ptr()), ldy,
+               k, route, ctypes.c_void_p(ws.data_ptr()), ws.numel(), s)
+        assert r == 0, mhdc.lib().mhdc_last_error_message()
+        assert torch.equal(Yb[:, :m.n].contiguous().view(torch.int64), ref.view(torch.int64)), route
+        assert bool((Yb[:, m.n:] == -3.0).all()), route
+    if m.n > 0:
+        x_last = Xc[k - 1].cpu().numpy()
+        assert_oracle_bits(ref[k - 1], want_last(x_last), "last column")
+    h.close()
+
+
 def test_spmm_ws_graph_replay():
     """Route 2 captured in a graph (it allocates nothing and records no
     memset): four replays on fresh inputs, with eager work and
