@@ -137,7 +137,6 @@ SpmvArgs make_args(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, 
     a.uniform = a.has_dia && (m.n_blk == 1 || (m.n_b % (64 * v)) == 0);
     a.remap = m.launch.xcd_remap;
     a.pairs = 0;
-    a.y_cols = 0;
     return a;
 }
 

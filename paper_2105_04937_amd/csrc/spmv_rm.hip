@@ -14,46 +14,47 @@ using KernelFn = void (*)(SpmvArgs);
 // columns with both parts the compiler took 132 VGPRs and three fitted; the
 // cap costs a 20-byte spill and took the partially diagonal 192^3 case at
 // 16 columns from 2.47 to 2.13 ms).  64-lane tiles are LDS-bound at one.
-template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
+// YC: Y stored by column (the workspace route of column-major products).
+template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG, bool YC>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG == 256 ? 4 : 1, 8))) void k_spmm_rm(SpmvArgs a)
 {
     __shared__ double s_lds[HAS_REM ? (TileShapeRm<WG, KC>::LDS_BYTES + 7) / 8 : 1];
     const int tile = a.remap ? xcd_tile(blockIdx.x, gridDim.x, a.remap) : (int)blockIdx.x;
-    spmv_tile_rm<WG, KC, HAS_DIA, HAS_REM, RG>(a, tile, s_lds);
+    spmv_tile_rm<WG, KC, HAS_DIA, HAS_REM, RG, YC>(a, tile, s_lds);
 }
 
 // parts: 1 = DIA part, 2 = CSR part, 4 = CSR part by row gathers
-template <int WG, int KC>
+template <int WG, int KC, bool YC>
 KernelFn pick_rm_parts(int parts)
 {
     switch (parts) {
     case 1:
-    case 5: return (KernelFn)k_spmm_rm<WG, KC, true, false, false>;
-    case 2: return (KernelFn)k_spmm_rm<WG, KC, false, true, false>;
-    case 3: return (KernelFn)k_spmm_rm<WG, KC, true, true, false>;
-    case 6: return (KernelFn)k_spmm_rm<WG, KC, false, true, true>;
-    case 7: return (KernelFn)k_spmm_rm<WG, KC, true, true, true>;
+    case 5: return (KernelFn)k_spmm_rm<WG, KC, true, false, false, YC>;
+    case 2: return (KernelFn)k_spmm_rm<WG, KC, false, true, false, YC>;
+    case 3: return (KernelFn)k_spmm_rm<WG, KC, true, true, false, YC>;
+    case 6: return (KernelFn)k_spmm_rm<WG, KC, false, true, true, YC>;
+    case 7: return (KernelFn)k_spmm_rm<WG, KC, true, true, true, YC>;
     }
     return nullptr;
 }
 
-template <int WG>
+template <int WG, bool YC>
 KernelFn pick_rm_kc(int kc, int parts)
 {
     switch (kc) {
-    case 2: return pick_rm_parts<WG, 2>(parts);
-    case 4: return pick_rm_parts<WG, 4>(parts);
-    case 8: return pick_rm_parts<WG, 8>(parts);
-    case 16: return pick_rm_parts<WG, 16>(parts);
+    case 2: return pick_rm_parts<WG, 2, YC>(parts);
+    case 4: return pick_rm_parts<WG, 4, YC>(parts);
+    case 8: return pick_rm_parts<WG, 8, YC>(parts);
+    case 16: return pick_rm_parts<WG, 16, YC>(parts);
     }
     return nullptr;
 }
 
-KernelFn pick_rm(int wg, int kc, int parts)
+KernelFn pick_rm(int wg, int kc, int parts, bool y_cols)
 {
     switch (wg) {
-    case 64: return pick_rm_kc<64>(kc, parts);
-    case 256: return pick_rm_kc<256>(kc, parts);
+    case 64: return y_cols ? pick_rm_kc<64, true>(kc, parts) : pick_rm_kc<64, false>(kc, parts);
+    case 256: return y_cols ? pick_rm_kc<256, true>(kc, parts) : pick_rm_kc<256, false>(kc, parts);
     }
     return nullptr;
 }
@@ -176,13 +177,13 @@ int launch_rm_kernel(const BdcMatrix &m, const double *X, int64_t ldx, double *Y
         k_zero_rows<<<dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, stream>>>(Y, ldy,
                                                                                       m.n, k);
     } else {
-        KernelFn fn = pick_rm(wg, rm_columns(k), (has_dia ? 1 : 0) | (has_rem ? 2 : 0) |
-                                                     (rm_row_gather(m) ? 4 : 0));
+        KernelFn fn = pick_rm(wg, rm_columns(k),
+                              (has_dia ? 1 : 0) | (has_rem ? 2 : 0) | (rm_row_gather(m) ? 4 : 0),
+                              y_cols);
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
         SpmvArgs a = make_args(m, X, ldx, Y, ldy, k, 1);
         a.pairs = rm_pairs(X, ldx, y_cols ? X : Y, y_cols ? ldx : ldy);
-        a.y_cols = y_cols ? 1 : 0;
         const int64_t tiles = ((int64_t)m.n + wg - 1) / wg;
         if (tiles > INT32_MAX)
             return set_error(MHDC_ERR_SIZE, "too many tiles");

@@ -63,7 +63,6 @@ struct SpmvArgs {
     int32_t remap;
     const uint32_t *rem_mask;  // one bit per 64 rows, or null: test rem_ptr
     int32_t pairs;             // row-major kernel: 16-byte accesses of column pairs
-    int32_t y_cols;            // row-major kernel: Y stored by column (Y[r*ldy + i])
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

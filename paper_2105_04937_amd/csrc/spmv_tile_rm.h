@@ -114,7 +114,10 @@ __device__ inline void rm_store(double *p, int nl, bool pairs, const double (&v)
 // for its own rows' entries (rows of similar structure, such as stencils,
 // then read neighbouring rows of X in one load); otherwise the rounded
 // products are staged (independent gathers, best for scattered columns).
-template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG>
+// YC: Y is stored by column (element (i, r) at Y[r*ldy + i]) instead of by
+// row; a template parameter, so that the kernels storing by row carry no
+// trace of it (a runtime branch cost the 16-column kernel 3 %).
+template <int WG, int KC, bool HAS_DIA, bool HAS_REM, bool RG, bool YC = false>
 __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
 {
     // products are rounded before they are added: no multiply-add fusion
@@ -321,7 +324,7 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
         }
     }
 
-    if (a.y_cols) {
+    if constexpr (YC) {
         if constexpr (HAS_REM) {
             // Y by column through LDS: the wavefront puts its 64 rows x KC
             // columns in its own region (column stride 65 doubles), then
