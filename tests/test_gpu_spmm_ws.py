@@ -281,27 +281,54 @@ def test_spmm_ws_graph_replay():
     h.close()
 
 
+@pytest.fixture(scope="module")
+def full_matrices():
+    """The two full-size matrices, generated once for the module."""
+    say("generating partially diagonal 27-point 192^3 and heptadiagonal 256^3")
+    return {"partial192": synth.partially_diagonal(192, 3), "hepta256": synth.heptadiagonal(256, 2)}
+
+
 @pytest.mark.slow
-def test_spmm_ws_full_size_16():
-    """The partially diagonal 192^3 matrix at n_b = 128 with 16 right-hand
-    sides: the default route is the row-major one, and every column equals
-    the column-major kernel's bits (itself pinned to the oracle at this
-    size); column 0 is the oracle's Fig. 16 kernel."""
-    say("case: spmm_ws full size partial192 k=16")
-    m = synth.partially_diagonal(192, 3)
+@pytest.mark.parametrize("case", ["partial192 M-HDC", "partial192 HDC", "partial192 CSR",
+                                  "hepta256 M-HDC"])
+def test_spmm_ws_full_size_16(case, full_matrices):
+    """16 right-hand sides at full size: on the partially diagonal 192^3
+    matrix (n_b = 128) every handle's default route is the row-major one; on
+    the heptadiagonal 256^3 matrix (n_b = 256, no CSR part) route 2 is
+    forced, which stores Y by column straight from the lanes.  Every column
+    equals the column-major kernel's bits (itself pinned to the oracle at
+    these sizes), and column 0 the oracle's sequential kernel of the
+    handle's format (Figs. 3, 8, 16)."""
+    name, fmt = case.split()
+    say("case: spmm_ws full size %s" % case)
+    m = full_matrices[name]
     d = dev(m)
-    h = mhdc.MHDCMatrix.from_csr(*d, 128, 0.6)
+    nb = 128 if name == "partial192" else 256
+    if fmt == "M-HDC":
+        h = mhdc.MHDCMatrix.from_csr(*d, nb, 0.6)
+    elif fmt == "HDC":
+        h = mhdc.HDCMatrix.from_csr(*d, 0.6)
+    else:
+        h = mhdc.CSRMatrix.from_csr(*d)
+    del d
     k = 16
-    assert h.ws_route(k) == 2
+    route = 0 if name == "partial192" else 2
+    if route == 0:
+        assert h.ws_route(k) == 2
     X = torch.empty((k, m.n), dtype=torch.float64, device="cuda")
     x0 = synth.vector(m.n, 3)
     X[0] = torch.from_numpy(x0).cuda()
     for r in range(1, k):
         X[r] = torch.from_numpy(synth.vector(m.n, 100 + r)).cuda()
     Yd = h.spmm(X)
-    Y = h.spmm_ws(X, route=0)
+    Y = h.spmm_ws(X, route=route)
     assert torch.equal(Y.view(torch.int64), Yd.view(torch.int64))
     del Yd
-    ref = oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, 128, 0.6)
-    assert_oracle_bits(Y[0], oracle.mhdc_spmv(ref, x0), "column 0")
+    if fmt == "M-HDC":
+        want = oracle.mhdc_spmv(oracle.mhdc_from_csr(m.rowptr, m.colind, m.val, nb, 0.6), x0)
+    elif fmt == "HDC":
+        want = oracle.hdc_spmv(oracle.hdc_from_csr(m.rowptr, m.colind, m.val, 0.6), x0)
+    else:
+        want = oracle.csr_spmv(m.rowptr, m.colind, m.val, x0, 0)
+    assert_oracle_bits(Y[0], want, "column 0")
     h.close()
