@@ -146,9 +146,9 @@ int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const do
 // where the CSR part is light (at most 6 entries per row): its values and
 // columns then stage in a few large chunks, where staged products at 16
 // columns take 256 entries per chunk and two barriers each.  Measured on
-// MI355X with 1.1-5.1 entries per row next to a DIA part: 2-3 % faster on
-// average at 4, 8 and 16 columns (from 3 % slower to 8 % faster); with 15-18
-// per row the staged products stay ahead (up to 20 %).
+// MI355X with 1.1-5.1 entries per row next to a DIA part: 2-5 % faster on
+// average at 4, 8 and 16 columns (from 2 % slower to 7 % faster); with 15-18
+// per row the better variant changes with the column count.
 bool rm_row_gather(const BdcMatrix &m)
 {
     if (m.launch.csr_mode == 0)

@@ -189,6 +189,27 @@ __device__ inline void spmv_tile_rm(const SpmvArgs &a, int64_t tile, void *lds)
                             const int32_t lo = rs > cb ? rs : cb;
                             const int32_t hi = re < ce ? re : ce;
                             int32_t e = lo;
+                            // four entries at once up to 8 columns (twice the
+                            // gathers in flight; at 16 columns the registers
+                            // are spent), then two, then one: ascending order
+                            if constexpr (KC <= 8) {
+                                for (; e + 4 <= hi; e += 4) {
+                                    double x0[P], x1[P], x2[P], x3[P];
+                                    rm_load<P>(X + (int64_t)s_col[e - cb] * ldx + c0, nl, pairs, x0);
+                                    rm_load<P>(X + (int64_t)s_col[e + 1 - cb] * ldx + c0, nl, pairs, x1);
+                                    rm_load<P>(X + (int64_t)s_col[e + 2 - cb] * ldx + c0, nl, pairs, x2);
+                                    rm_load<P>(X + (int64_t)s_col[e + 3 - cb] * ldx + c0, nl, pairs, x3);
+                                    const double w0 = s_val[e - cb], w1 = s_val[e + 1 - cb];
+                                    const double w2 = s_val[e + 2 - cb], w3 = s_val[e + 3 - cb];
+#pragma unroll
+                                    for (int p = 0; p < P; p++) {
+                                        acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w0, x0[p]));
+                                        acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w1, x1[p]));
+                                        acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w2, x2[p]));
+                                        acc[q][p] = __dadd_rn(acc[q][p], __dmul_rn(w3, x3[p]));
+                                    }
+                                }
+                            }
                             for (; e + 2 <= hi; e += 2) {
                                 const double w0 = s_val[e - cb], w1 = s_val[e + 1 - cb];
                                 double x0[P], x1[P];
