@@ -64,10 +64,11 @@ struct TileShapeRm {
     static_assert(CH % (WG / 64 * GRPI) == 0, "chunk splits evenly over the slots");
     // products per lane and chunk
     static constexpr int PER_LANE = CH / (WG / 64) / GRPI;
-    // diagonals in flight (two at 8 columns: 2-5 % faster than one; four up
-    // to 4 columns, where a diagonal's X rows take few registers: 1-2 %
-    // faster than two, and the small matrices of a batch gain the most)
-    static constexpr int U = KC >= 16 ? 1 : (KC <= 4 ? 4 : 2);
+    // diagonals in flight: four up to 8 columns (at 8 the DIA-only kernel
+    // then holds 4 instead of 6 waves per SIMD and is still 8 % faster than
+    // with two on the 7-point 256^3 matrix; 1-2 % at 3 and 4 columns), one
+    // at 16 (two gained nothing there: registers)
+    static constexpr int U = KC >= 16 ? 1 : 4;
 };
 
 typedef double rm_pair __attribute__((ext_vector_type(2)));
