@@ -171,8 +171,9 @@ int mhdc_spmm(mhdc_handle h, const double *X, int64_t ldx, double *Y,
  * csr_mode (mhdc_launch) picks the CSR-part variant: 1 = staged products
  * (independent gathers; scattered columns), 2 = staged values and columns
  * with each lane gathering for its own rows (rows that repeat their
- * neighbours' offsets, such as stencils), 0 = 2 when row_repeat >= 0.5
- * or the CSR part holds at most 6 entries per row (R <= 6n), else 1.
+ * neighbours' offsets, such as stencils), 0 = 2 when row_repeat >= 0.5,
+ * the CSR part holds at most 6 entries per row (R <= 6n) or 5 <= k <= 8,
+ * else 1.
  * rows_per_lane and rhs_group do not apply.  Each lane carries
  * adjacent columns; X and Y 16-byte aligned with even ldx and ldy let it
  * move them with 16-byte loads and stores (the fast case; otherwise 8-byte

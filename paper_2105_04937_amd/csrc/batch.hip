@@ -342,7 +342,7 @@ int upload_items(mhdc_batch_s *b, int32_t wg, const double *const *X, const int6
         it.user = i;
         it.a = make_args(m, X[i], lx, Y[i], ly, k, 1);
         it.kc = b->rowmajor ? rm_columns(k) : kc_for(k < BATCH_MAX_KC ? k : BATCH_MAX_KC);
-        it.rg = (b->rowmajor ? rm_row_gather(m) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
+        it.rg = (b->rowmajor ? rm_row_gather(m, it.kc) : row_gather(m.launch.csr_mode, it.kc)) ? 1 : 0;
         it.a.pairs = b->rowmajor && rm_pairs(X[i], lx, Y[i], ly) ? 1 : 0;
         it.tile_begin = tiles;
         tiles_of[slot] = ((int64_t)m.n + wg - 1) / wg;

@@ -125,9 +125,10 @@ int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const do
 bool rm_pairs(const double *X, int64_t ldx, const double *Y, int64_t ldy);
 int rm_columns(int32_t k);  // accumulator width of the row-major kernel (2..16)
 // Row-major CSR part by row gathers (csr_mode 2, or csr_mode 0 and rows that
-// mostly repeat their neighbours' column offsets or a CSR part of at most 6
-// entries per row) rather than staged products.
-bool rm_row_gather(const BdcMatrix &m);
+// mostly repeat their neighbours' column offsets, a CSR part of at most 6
+// entries per row, or an accumulator width kc of 8) rather than staged
+// products.
+bool rm_row_gather(const BdcMatrix &m, int kc);
 int launch_spmm_rm(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,
                    int32_t k, hipStream_t stream);
 // Column-major right-hand sides with a caller workspace: route 1 = the

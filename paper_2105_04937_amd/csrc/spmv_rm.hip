@@ -142,17 +142,21 @@ int check_operands_rm(const BdcMatrix &m, const double *X, int64_t ldx, const do
     return MHDC_OK;
 }
 
-// Default: row gathers where rows repeat their neighbours' offsets, and
-// where the CSR part is light (at most 6 entries per row): its values and
-// columns then stage in a few large chunks, where staged products at 16
-// columns take 256 entries per chunk and two barriers each.  Measured on
-// MI355X with 1.1-5.1 entries per row next to a DIA part: 2-5 % faster on
-// average at 4, 8 and 16 columns (from 2 % slower to 7 % faster); with 15-18
-// per row the better variant changes with the column count.
-bool rm_row_gather(const BdcMatrix &m)
+// Default (csr_mode 0): row gathers where rows repeat their neighbours'
+// offsets, where the CSR part is light (at most 6 entries per row: its
+// values and columns then stage in a few large chunks, where staged
+// products at 16 columns take 256 entries per chunk and two barriers each)
+// and at an accumulator width of 8 columns (k = 5..8), where each lane's
+// four gathers of 16 bytes in flight beat the staged products' LDS round
+// trip.  Measured on MI355X: 1.1-5.1 entries per row next to a DIA part
+// 2-5 % faster on average at 4, 8 and 16 columns; at 8 columns 5-20 %
+// faster on every handle tried with 7.7-19.9 entries per row, whole-matrix
+// CSR handles included; at 4 columns such CSR parts keep staged products
+// (up to 15 % ahead), as they do at 16.
+bool rm_row_gather(const BdcMatrix &m, int kc)
 {
     if (m.launch.csr_mode == 0)
-        return m.row_repeat >= 0.5 || (m.R > 0 && m.R <= 6 * (int64_t)m.n);
+        return m.row_repeat >= 0.5 || (m.R > 0 && m.R <= 6 * (int64_t)m.n) || kc == 8;
     return m.launch.csr_mode == 2;
 }
 
@@ -185,7 +189,8 @@ int launch_rm_kernel(const BdcMatrix &m, const double *X, int64_t ldx, double *Y
                                                                                       m.n, k);
     } else {
         KernelFn fn = pick_rm(wg, rm_columns(k),
-                              (has_dia ? 1 : 0) | (has_rem ? 2 : 0) | (rm_row_gather(m) ? 4 : 0),
+                              (has_dia ? 1 : 0) | (has_rem ? 2 : 0) |
+                                  (rm_row_gather(m, rm_columns(k)) ? 4 : 0),
                               y_cols);
         if (!fn)
             return set_error(MHDC_ERR_NOT_SUPPORTED, "no kernel variant for this launch shape");
