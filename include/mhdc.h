@@ -205,7 +205,7 @@ int mhdc_spmm_ws(mhdc_handle h, const double *X, int64_t ldx, double *Y,
  * 8*n*k', the row-major copy of X. */
 int mhdc_spmm_workspace_bytes(mhdc_handle h, int32_t k, size_t *bytes);
 /* The route mhdc_spmm_ws takes for route 0 and k right-hand sides:
- * 2 when k >= 2 and k * lone_per_row (mhdc_info) >= 4, else 1.  A lone
+ * 2 when k >= 2 and k * lone_per_row (mhdc_info) >= 2, else 1.  A lone
  * entry's gather from column-major X touches one cache line per column
  * that no neighbouring row shares; the row-major copy serves all k
  * columns from one line. */

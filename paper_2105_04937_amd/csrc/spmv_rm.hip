@@ -229,14 +229,14 @@ size_t spmm_ws_bytes(const BdcMatrix &m, int32_t k)
 
 // Lone gathers cost one cache line per column from column-major X and about
 // one line per row from the row-major copy (k <= 16 doubles), against 2k
-// extra doubles per row of transposition.  Measured on MI355X, the route
-// through the row-major kernel gained 1.2-1.6x at 1 lone entry per row and
-// k = 4..16, 1.07-1.13x at 2-2.4 per row and k = 2, 1.4-2.2x at k = 4..16,
-// and lost up to 0.5x on stencil matrices whose CSR part has almost none
-// (and 0.9x at 1 per row and k = 2).
+// extra doubles per row of transposition.  Measured on MI355X: at 1 lone
+// entry per row the route through the row-major kernel gained 1.13x at k = 2
+// and 1.4-1.7x at k = 4..16; at 2-2.4 per row 1.07-1.33x at k = 2 and
+// 1.4-2.4x beyond; with almost none (stencil remainders) it ranged from
+// 0.5x to 1.07x.
 bool spmm_ws_prefers_rm(const BdcMatrix &m, int32_t k)
 {
-    return k >= 2 && m.R > 0 && m.lone_per_row * k >= 4.0;
+    return k >= 2 && m.R > 0 && m.lone_per_row * k >= 2.0;
 }
 
 int launch_spmm_ws(const BdcMatrix &m, const double *X, int64_t ldx, double *Y, int64_t ldy,

@@ -79,7 +79,7 @@ def _lone_per_row(ptr, col):
 
 def test_lone_count_and_route_rule():
     """lone_per_row of the CSR part equals the host brute force exactly;
-    the default route is 2 exactly when k >= 2 and k * lone_per_row >= 4."""
+    the default route is 2 exactly when k >= 2 and k * lone_per_row >= 2."""
     cases = [("7-point 12^3", synth.heptadiagonal(12, 1)),
              ("27-point 10^3 octant drops", synth.partially_diagonal(10, 2)),
              ("27-point 10^3 one random column", synth.partially_diagonal(
@@ -100,7 +100,7 @@ def test_lone_count_and_route_rule():
                 want = _lone_per_row(t["rem_ptr"].cpu().numpy(), t["rem_col"].cpu().numpy())
             assert inf["lone_per_row"] == want, (name, kind, inf["lone_per_row"], want)
             for k in range(1, 17):
-                route = 2 if (k >= 2 and inf["R"] > 0 and want * k >= 4.0) else 1
+                route = 2 if (k >= 2 and inf["R"] > 0 and want * k >= 2.0) else 1
                 assert h.ws_route(k) == route, (name, kind, k)
                 seen.add(route)
             h.close()
