@@ -25,17 +25,19 @@
 //   * DIA part: each lane loads the value of row wave_base + lane (one
 //     coalesced load per diagonal, non-temporal) and the lanes of row slot s
 //     read the value of their row q from lane s + RPI*q (cross-lane read).
-//   * CSR part: per chunk of the tile's entries, the wavefronts form the
-//     rounded products w * X[col*ldx + c'] and store them in LDS, with four
-//     columns per lane from KC = 4 on (independent gathers of two 16-byte
-//     loads each, eight or more loads in flight per lane; each value and
-//     column index is then read by KC/4 lanes instead of KC/2; the DIA
-//     part keeps pairs, since with four columns per lane each 16-byte load
-//     instruction covers only half of every row's cache line); each lane
-//     then adds
-//     the products of its rows' entries in column order, finding them
-//     through the tile's row pointers, which are staged in LDS once per
-//     tile.
+//   * CSR part, staged products: per chunk of the tile's entries, the
+//     wavefronts form the rounded products w * X[col*ldx + c'] and store
+//     them in LDS, with four columns per lane from KC = 4 on (independent
+//     gathers of two 16-byte loads each, eight or more loads in flight per
+//     lane; each value and column index is then read by KC/4 lanes instead
+//     of KC/2; the DIA part keeps pairs, since with four columns per lane
+//     each 16-byte load instruction covers only half of every row's cache
+//     line); each lane then adds the products of its rows' entries in
+//     column order, finding them through the tile's row pointers, which
+//     are staged in LDS once per tile.
+//   * CSR part, row gathers (RG): values and columns are staged instead and
+//     each lane gathers the X rows of its own rows' entries, four at once up
+//     to KC = 8 (the launcher's choice between the two is rm_row_gather).
 #pragma once
 
 #include "spmv_tile.h"
